@@ -1,0 +1,878 @@
+// Reference (oracle) implementation of the reacting-flow right-hand side.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, FP64 CPU statement
+// of what the GPU library computes.  Only the test suite, the smoke check and
+// the CPU-baseline leg of the benchmark may load it; the product path never
+// does.  It shares no code, header, table or constant generator with the HIP
+// library: every formula below is written out here on its own.
+//
+// Paper: Maeda et al., "An integrated heterogeneous computing framework for
+// ensemble simulations of laser-induced ignition" (arXiv 2202.02319).
+//   governing equations            Sec. 5.1 "Governing equations", eqs. (1)-(3)
+//   ideal-gas closure              eq. (4)
+//   Wilke viscosity, NASA c_p      Sec. 5.1, text after eq. (4)
+//   heat flux                      eq. (5)
+//   diffusion velocity             eq. (6), Bird mixture-averaged D_s with
+//                                  Hirschfelder binary D_ij
+//   finite-rate Arrhenius chem.    Sec. 5.1 "Combustion chemistry"
+//   conservative FD, TENO6, 2nd-order central diffusion, SSP-RK3
+//                                  Sec. 5.2 "Numerical method"
+//   laser source q_L               Sec. 6.3.1, eq. (laser-qs)
+//
+// Structure: every step is its own loop, in the order the method defines it:
+//   1. per cell: primitives (Newton for T), transport, chemistry, laser;
+//   2. per node: the Ducros-type sensor;
+//   3. per direction and per face: convective flux (central or TENO6 on a
+//      local Lax-Friedrichs split) and diffusive flux;
+//   4. per cell: flux differences plus sources.
+// No blocking, no fusion.  Everything is templated on the scalar type so the
+// same code, run on Dual numbers, gives the forward-mode tangent with all
+// discrete switches (TENO cut-off, sensor, argmax of the LF speed, Newton
+// iteration count) taken on the real part.
+//
+// Parity status of each part is listed in the test suite; the whole RHS has
+// no printed worked example in the paper, so its absolute values are pinned
+// only through closed forms, invariants and textbook special cases.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace orc {
+
+// ---------------------------------------------------------------- constants
+// Exact SI values (2019 SI): k_B, N_A; R_u = N_A k_B.
+static const double kB = 1.380649e-23;
+static const double NA = 6.02214076e23;
+static const double Ru = 8.31446261815324;
+static const double P0 = 101325.0;   // reference pressure of the standard state
+static const double PI = 3.14159265358979323846;
+
+enum { OK = 0, EINVAL = 1, ENONFINITE = 4, ENEWTON = 5, ETRANGE = 6 };
+enum { CHEM_OFF = 1u, VISC_OFF = 2u, FORCE_CENTRAL = 4u, FORCE_TENO = 8u };
+
+// ------------------------------------------------------------- dual numbers
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+static inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+static inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+static inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+static inline Dual exp(Dual a) { double e = std::exp(a.v); return Dual(e, e * a.d); }
+static inline Dual log(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
+static inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+static inline Dual pow(Dual a, double b) {
+  double p = std::pow(a.v, b);
+  return Dual(p, b * std::pow(a.v, b - 1.0) * a.d);
+}
+static inline Dual fabs(Dual a) { return a.v < 0 ? -a : a; }
+static inline double val(double a) { return a; }
+static inline double val(const Dual& a) { return a.v; }
+using std::exp; using std::log; using std::sqrt; using std::pow; using std::fabs;
+
+// ------------------------------------------------------------------- tables
+struct Case {
+  int ns, nr;
+  std::vector<double> W, a7, sig, epsk, lnA, beta, Ea;   // a7: [ns][7]
+  std::vector<int> nuf, nur;                             // [nr][ns]
+  double Tmin, Tmax;
+  int n[3];
+  std::vector<double> xnode[3], xin[3], xif[3];          // coordinate, node & face metric
+  double L[3];
+  double theta_c, psi_c, CT, cfl;
+  unsigned flags;
+  long long N() const { return (long long)n[0] * n[1] * n[2]; }
+  long long idx(int i, int j, int k) const { return ((long long)k * n[1] + j) * n[0] + i; }
+};
+
+template <class S> struct Params {   // differentiable parameters
+  std::vector<S> lnA;                // per reaction
+  S E;                               // deposited energy
+  S xc[3];                           // kernel centre
+  double sr, t0, st;                 // kernel radius, delay, duration
+  bool on;
+};
+
+static inline int wrap(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+
+// ------------------------------------------------------------ NASA-7 thermo
+// c_p/R, h/(RT), s/R of one species from the 7-coefficient polynomial
+// (McBride et al.).  The paper names the 9-coefficient variant; its tables
+// are not available, so the seeded 7-coefficient form is used.
+template <class S> static inline S cp_R(const double* a, S T) {
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+}
+template <class S> static inline S h_RT(const double* a, S T) {
+  return a[0] + T * (a[1] / 2.0 + T * (a[2] / 3.0 + T * (a[3] / 4.0 + T * (a[4] / 5.0)))) + a[5] / T;
+}
+template <class S> static inline S s_R(const double* a, S T) {
+  return a[0] * log(T) + T * (a[1] + T * (a[2] / 2.0 + T * (a[3] / 3.0 + T * (a[4] / 4.0)))) + a[6];
+}
+
+// ------------------------------------------------------ per-cell quantities
+template <class S> struct Cell {
+  S rho, u[3], T, p, c, W, cp, mu, lam;
+  std::vector<S> Y, X, h, D, wdot;     // h: J/kg; D: mixture-averaged diffusivity
+  S hrr, qL;
+};
+
+// Collision-integral fits of Neufeld, Janzen & Aziz (1972).
+template <class S> static inline S omega22(S Ts) {
+  return 1.16145 * pow(Ts, -0.14874) + 0.52487 * exp(-0.77320 * Ts) + 2.16178 * exp(-2.43787 * Ts);
+}
+template <class S> static inline S omega11(S Ts) {
+  return 1.06036 * pow(Ts, -0.15610) + 0.19300 * exp(-0.47635 * Ts) + 1.03587 * exp(-1.52996 * Ts) +
+         1.76474 * exp(-3.89411 * Ts);
+}
+
+// Species viscosity, Chapman-Enskog.
+template <class S> static S mu_species(const Case& C, int s, S T) {
+  double m = C.W[s] / NA;
+  double sg = C.sig[s];
+  return (5.0 / 16.0) * sqrt(PI * m * kB * T) / (PI * sg * sg * omega22(T / C.epsk[s]));
+}
+// Binary diffusion coefficient (Hirschfelder, Curtiss & Bird).
+template <class S> static S D_binary(const Case& C, int i, int j, S T, S p) {
+  double mij = 1.0 / (NA * (1.0 / C.W[i] + 1.0 / C.W[j]));
+  double sg = 0.5 * (C.sig[i] + C.sig[j]);
+  double ek = std::sqrt(C.epsk[i] * C.epsk[j]);
+  S kT = kB * T;
+  return (3.0 / 16.0) * sqrt(2.0 * PI * kT * kT * kT / mij) / (p * PI * sg * sg * omega11(T / ek));
+}
+
+// Step 1: primitives and thermodynamics (eqs. 1-4).  Returns an error code.
+template <class S>
+static int primitives(const Case& C, const S* Uc, double Tguess, Cell<S>& z) {
+  const int ns = C.ns;
+  z.Y.assign(ns, S(0)); z.X.assign(ns, S(0)); z.h.assign(ns, S(0));
+  z.D.assign(ns, S(0)); z.wdot.assign(ns, S(0));
+  for (int v = 0; v < ns + 4; ++v)
+    if (!std::isfinite(val(Uc[v]))) return ENONFINITE;
+  S rho = 0;
+  for (int s = 0; s < ns; ++s) rho += Uc[s];
+  if (!(val(rho) > 0)) return ENONFINITE;
+  z.rho = rho;
+  for (int s = 0; s < ns; ++s) z.Y[s] = Uc[s] / rho;
+  for (int m = 0; m < 3; ++m) z.u[m] = Uc[ns + m] / rho;
+  S ke = 0.5 * (z.u[0] * z.u[0] + z.u[1] * z.u[1] + z.u[2] * z.u[2]);
+  S e = Uc[ns + 3] / rho - ke;
+  // Newton on e(T) = sum_s Y_s (h_s(T) - R_u T / W_s); converge, then one more step.
+  S T = Tguess;
+  bool conv = false;
+  for (int it = 0; it < 50; ++it) {
+    S eT = 0, cv = 0;
+    for (int s = 0; s < ns; ++s) {
+      const double* a = &C.a7[7 * s];
+      double RW = Ru / C.W[s];
+      eT += z.Y[s] * RW * T * (h_RT(a, T) - 1.0);
+      cv += z.Y[s] * RW * (cp_R(a, T) - 1.0);
+    }
+    S dT = (eT - e) / cv;
+    T = T - dT;
+    if (!std::isfinite(val(T)) || !(val(T) > 0)) return ENEWTON;
+    if (std::fabs(val(dT)) <= 1e-12 * std::fabs(val(T))) {
+      S eT2 = 0, cv2 = 0;
+      for (int s = 0; s < ns; ++s) {
+        const double* a = &C.a7[7 * s];
+        double RW = Ru / C.W[s];
+        eT2 += z.Y[s] * RW * T * (h_RT(a, T) - 1.0);
+        cv2 += z.Y[s] * RW * (cp_R(a, T) - 1.0);
+      }
+      T = T - (eT2 - e) / cv2;
+      conv = true;
+      break;
+    }
+  }
+  if (!conv) return ENEWTON;
+  if (val(T) < C.Tmin || val(T) > C.Tmax) return ETRANGE;
+  z.T = T;
+  S iW = 0;
+  for (int s = 0; s < ns; ++s) iW += z.Y[s] / C.W[s];
+  z.W = 1.0 / iW;
+  z.p = rho * Ru * T / z.W;                          // eq. (4)
+  S cp = 0;
+  for (int s = 0; s < ns; ++s) {
+    const double* a = &C.a7[7 * s];
+    double RW = Ru / C.W[s];
+    z.X[s] = z.Y[s] * z.W / C.W[s];
+    z.h[s] = RW * T * h_RT(a, T);
+    cp += z.Y[s] * RW * cp_R(a, T);
+  }
+  z.cp = cp;
+  S cv = cp - Ru / z.W;
+  z.c = sqrt(cp / cv * z.p / rho);
+  return OK;
+}
+
+// Step 1b: mixture-averaged transport: Wilke mu, Wilke-form lambda with
+// Eucken species conductivities, Bird mixture diffusivities.
+template <class S> static void transport(const Case& C, Cell<S>& z) {
+  const int ns = C.ns;
+  std::vector<S> mus(ns), lams(ns);
+  for (int s = 0; s < ns; ++s) {
+    const double* a = &C.a7[7 * s];
+    double RW = Ru / C.W[s];
+    mus[s] = mu_species(C, s, z.T);
+    S cps = RW * cp_R(a, z.T);
+    lams[s] = mus[s] * (cps + 1.25 * RW);             // Eucken
+  }
+  S mu = 0, lam = 0;
+  for (int i = 0; i < ns; ++i) {
+    S den = 0;
+    for (int j = 0; j < ns; ++j) {
+      S r = 1.0 + sqrt(mus[i] / mus[j]) * std::pow(C.W[j] / C.W[i], 0.25);
+      S phi = r * r / std::sqrt(8.0 * (1.0 + C.W[i] / C.W[j]));
+      den += z.X[j] * phi;
+    }
+    mu += z.X[i] * mus[i] / den;
+    lam += z.X[i] * lams[i] / den;
+  }
+  z.mu = mu;
+  z.lam = lam;
+  for (int s = 0; s < ns; ++s) {
+    S den = 0;
+    for (int j = 0; j < ns; ++j) {
+      if (j == s) continue;
+      S xj = val(z.X[j]) > 0 ? z.X[j] : S(0);
+      den += xj / D_binary(C, s, j, z.T, z.p);
+    }
+    if (val(den) < 1e-300) z.D[s] = D_binary(C, s, s, z.T, z.p);
+    else z.D[s] = (1.0 - z.Y[s]) / den;
+  }
+}
+
+// Step 1c: finite-rate chemistry with reverse rates from equilibrium constants.
+template <class S>
+static void chemistry(const Case& C, const Params<S>& P, const S* Uc, Cell<S>& z, double* rates = nullptr) {
+  const int ns = C.ns;
+  std::vector<S> G(ns), conc(ns);
+  S lnT = log(z.T);
+  for (int s = 0; s < ns; ++s) {
+    const double* a = &C.a7[7 * s];
+    G[s] = h_RT(a, z.T) - s_R(a, z.T);               // g_s/(R_u T)
+    conc[s] = Uc[s] / C.W[s];
+  }
+  S lnP = log(P0 / (Ru * z.T));
+  for (int s = 0; s < ns; ++s) z.wdot[s] = 0;
+  for (int j = 0; j < C.nr; ++j) {
+    S lnkf = P.lnA[j] + C.beta[j] * lnT - C.Ea[j] / (Ru * z.T);
+    S lnKc = 0;
+    int dnu = 0;
+    for (int s = 0; s < ns; ++s) {
+      int nu = C.nur[j * ns + s] - C.nuf[j * ns + s];
+      lnKc -= (double)nu * G[s];
+      dnu += nu;
+    }
+    lnKc += (double)dnu * lnP;
+    S kf = exp(lnkf);
+    S kb = exp(lnkf - lnKc);
+    S rf = kf, rb = kb;
+    for (int s = 0; s < ns; ++s) {
+      for (int m = 0; m < C.nuf[j * ns + s]; ++m) rf *= conc[s];
+      for (int m = 0; m < C.nur[j * ns + s]; ++m) rb *= conc[s];
+    }
+    S q = rf - rb;
+    if (rates) { rates[2 * j] = val(rf); rates[2 * j + 1] = val(rb); }
+    for (int s = 0; s < ns; ++s) {
+      int nu = C.nur[j * ns + s] - C.nuf[j * ns + s];
+      if (nu) z.wdot[s] += C.W[s] * (double)nu * q;
+    }
+  }
+  S hrr = 0;
+  for (int s = 0; s < ns; ++s) hrr -= z.h[s] * z.wdot[s];
+  z.hrr = hrr;
+}
+
+// Step 1d: laser deposition, a Gaussian in space (wrapped over the periodic
+// images) and time, normalised so that its space-time integral equals E.
+template <class S>
+static S laser_axis(const Case& C, const Params<S>& P, int a, int i) {
+  if (C.n[a] == 1) return S(1);
+  double Lp = C.L[a];
+  S r = C.xnode[a][i] - P.xc[a];
+  double shift = Lp * std::nearbyint(val(r) / Lp);   // minimum image (a discrete choice)
+  r = r - shift;
+  int M = (int)std::ceil(9.103 * P.sr / Lp - 0.5);
+  if (M < 0) M = 0;
+  S g = 0;
+  for (int m = -M; m <= M; ++m) {
+    S z = (r - (double)m * Lp) / P.sr;
+    g += exp(-0.5 * z * z);
+  }
+  return g;
+}
+template <class S>
+static S laser_q(const Case& C, const Params<S>& P, int i, int j, int k, double t) {
+  if (!P.on) return S(0);
+  int d = (C.n[0] > 1) + (C.n[1] > 1) + (C.n[2] > 1);
+  double norm = std::pow(2.0 * PI, 0.5 * (d + 1)) * std::pow(P.sr, d) * P.st;
+  double tt = (t - P.t0) / P.st;
+  return P.E / norm * laser_axis(C, P, 0, i) * laser_axis(C, P, 1, j) * laser_axis(C, P, 2, k) *
+         std::exp(-0.5 * tt * tt);
+}
+
+// ------------------------------------------------------------------- TENO6
+// Reconstruction at x_{i+1/2} from f[0..5] = f_{i-2..i+3} (Fu et al. 2016):
+// four candidate stencils, Jiang-Shu smoothness of each, sixth-order global
+// measure tau, sharp cut-off delta_k = [chi_k >= C_T], optimal weights d_k.
+template <class S> static S teno6(const S* f, double CT, double* detail = nullptr) {
+  double g[6];
+  for (int k = 0; k < 6; ++k) g[k] = val(f[k]);
+  // candidate reconstructions
+  S q0 = (-f[1] + 5.0 * f[2] + 2.0 * f[3]) / 6.0;               // {i-1,i,i+1}
+  S q1 = (2.0 * f[2] + 5.0 * f[3] - f[4]) / 6.0;                // {i,i+1,i+2}
+  S q2 = (2.0 * f[0] - 7.0 * f[1] + 11.0 * f[2]) / 6.0;         // {i-2,i-1,i}
+  S q3 = (3.0 * f[2] + 13.0 * f[3] - 5.0 * f[4] + f[5]) / 12.0; // {i..i+3}
+  // smoothness indicators: sum over derivative orders of the cell-i integral
+  const double c0a = g[1] - 2 * g[2] + g[3], c0b = g[1] - g[3];
+  const double c1a = g[2] - 2 * g[3] + g[4], c1b = 3 * g[2] - 4 * g[3] + g[4];
+  const double c2a = g[0] - 2 * g[1] + g[2], c2b = g[0] - 4 * g[1] + 3 * g[2];
+  const double c3a = -11 * g[2] + 18 * g[3] - 9 * g[4] + 2 * g[5];
+  const double c3b = 2 * g[2] - 5 * g[3] + 4 * g[4] - g[5];
+  const double c3c = -g[2] + 3 * g[3] - 3 * g[4] + g[5];
+  double b0 = 13.0 / 12.0 * c0a * c0a + 0.25 * c0b * c0b;
+  double b1 = 13.0 / 12.0 * c1a * c1a + 0.25 * c1b * c1b;
+  double b2 = 13.0 / 12.0 * c2a * c2a + 0.25 * c2b * c2b;
+  double b3 = 1.0 / 36.0 * c3a * c3a + 13.0 / 12.0 * c3b * c3b + 781.0 / 720.0 * c3c * c3c;
+  // six-point polynomial p(x) = sum a_k x^k with cell averages f (x in cell
+  // widths, origin at the centre of cell i); beta6 as a quadratic form in a_1..a_5.
+  double a1 = (341 * g[0] - 2785 * g[1] - 2590 * g[2] + 6670 * g[3] - 1895 * g[4] + 259 * g[5]) / 5760.0;
+  double a2 = -(g[0] - 12 * g[1] + 22 * g[2] - 12 * g[3] + g[4]) / 16.0;
+  double a3 = -(5 * g[0] + 11 * g[1] - 70 * g[2] + 94 * g[3] - 47 * g[4] + 7 * g[5]) / 144.0;
+  double a4 = (g[0] - 4 * g[1] + 6 * g[2] - 4 * g[3] + g[4]) / 24.0;
+  double a5 = -(g[0] - 5 * g[1] + 10 * g[2] - 10 * g[3] + 5 * g[4] - g[5]) / 120.0;
+  double b6 = a1 * a1 + 0.5 * a1 * a3 + 0.125 * a1 * a5 + 13.0 / 3.0 * a2 * a2 + 21.0 / 5.0 * a2 * a4 +
+              3129.0 / 80.0 * a3 * a3 + 14127.0 / 224.0 * a3 * a5 + 87617.0 / 140.0 * a4 * a4 +
+              252337135.0 / 16128.0 * a5 * a5;
+  double tau = std::fabs(b6 - (b1 + b2 + 4.0 * b0) / 6.0);
+  const double eps = 1e-40;
+  double r[4] = {1.0 + tau / (b0 + eps), 1.0 + tau / (b1 + eps), 1.0 + tau / (b2 + eps), 1.0 + tau / (b3 + eps)};
+  // gamma_k = r_k^6 and chi_k = gamma_k / sum gamma; evaluated relative to the
+  // largest r so that the sixth power cannot overflow (same ratios).
+  double rm = std::max(std::max(r[0], r[1]), std::max(r[2], r[3]));
+  double gsum = 0, gam[4];
+  for (int k = 0; k < 4; ++k) { double s = r[k] / rm; gam[k] = s * s * s * s * s * s; gsum += gam[k]; }
+  const double dk[4] = {9.0 / 20.0, 3.0 / 10.0, 1.0 / 20.0, 1.0 / 5.0};
+  double wsum = 0, w[4];
+  for (int k = 0; k < 4; ++k) { w[k] = (gam[k] / gsum >= CT) ? dk[k] : 0.0; wsum += w[k]; }
+  if (detail) {
+    const double d[15] = {b0, b1, b2, b3, b6, tau, gam[0] / gsum, gam[1] / gsum, gam[2] / gsum, gam[3] / gsum,
+                          w[0] / wsum, w[1] / wsum, w[2] / wsum, w[3] / wsum, 0.0};
+    for (int k = 0; k < 15; ++k) detail[k] = d[k];
+  }
+  return (w[0] * q0 + w[1] * q1 + w[2] * q2 + w[3] * q3) / wsum;
+}
+
+// ----------------------------------------------------------------- the RHS
+template <class S> struct Fields {
+  std::vector<Cell<S>> cell;
+  std::vector<double> theta;   // sensor per node
+};
+
+template <class S>
+static int eval_cells(const Case& C, const Params<S>& P, const S* U, double* T_io, double t,
+                      Fields<S>& F) {
+  const long long N = C.N();
+  const int nv = C.ns + 4;
+  F.cell.assign(N, Cell<S>());
+  int err = OK;
+#pragma omp parallel for schedule(static) reduction(max : err)
+  for (long long q = 0; q < N; ++q) {
+    std::vector<S> Uc(nv);
+    for (int v = 0; v < nv; ++v) Uc[v] = U[v * N + q];
+    Cell<S>& z = F.cell[q];
+    int e = primitives(C, Uc.data(), T_io[q], z);
+    if (e) { err = std::max(err, e); continue; }
+    transport(C, z);
+    if (!(C.flags & CHEM_OFF)) chemistry(C, P, Uc.data(), z);
+    else z.hrr = 0;
+    int i = q % C.n[0], j = (q / C.n[0]) % C.n[1], k = q / ((long long)C.n[0] * C.n[1]);
+    z.qL = laser_q(C, P, i, j, k, t);
+  }
+  if (err) return err;
+  for (long long q = 0; q < N; ++q) T_io[q] = val(F.cell[q].T);
+  // Step 2: dilatation/vorticity sensor at every node (second-order central).
+  F.theta.assign(N, 0.0);
+#pragma omp parallel for schedule(static)
+  for (long long q = 0; q < N; ++q) {
+    int i = q % C.n[0], j = (q / C.n[0]) % C.n[1], k = q / ((long long)C.n[0] * C.n[1]);
+    int c[3] = {i, j, k};
+    double g[3][3] = {{0}};   // g[a][m] = d u_m / d x_a
+    for (int a = 0; a < 3; ++a) {
+      if (C.n[a] == 1) continue;
+      int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+      cp[a] = wrap(c[a] + 1, C.n[a]);
+      cm[a] = wrap(c[a] - 1, C.n[a]);
+      const Cell<S>& zp = F.cell[C.idx(cp[0], cp[1], cp[2])];
+      const Cell<S>& zm = F.cell[C.idx(cm[0], cm[1], cm[2])];
+      for (int m = 0; m < 3; ++m) g[a][m] = C.xin[a][c[a]] * (val(zp.u[m]) - val(zm.u[m])) / 2.0;
+    }
+    double div = g[0][0] + g[1][1] + g[2][2];
+    double wx = g[1][2] - g[2][1], wy = g[2][0] - g[0][2], wz = g[0][1] - g[1][0];
+    double d2 = div * div;
+    F.theta[q] = d2 / (d2 + wx * wx + wy * wy + wz * wz + 1e-300);
+  }
+  return OK;
+}
+
+// Convective flux of variable v at a node along direction d.
+template <class S> static S node_flux(const Case& C, const S* Uc, const Cell<S>& z, int v, int d) {
+  const int ns = C.ns;
+  S un = z.u[d];
+  if (v < ns) return Uc[v] * un;
+  if (v < ns + 3) return Uc[v] * un + ((v - ns) == d ? z.p : S(0));
+  return (Uc[v] + z.p) * un;
+}
+
+// Step 3a: hybrid switch at face i+1/2: TENO where the sensor exceeds its
+// threshold anywhere on the six-point stencil or the pressure jump across the
+// face is large; the central flux elsewhere.  Decisions use the real part.
+template <class S>
+static bool use_teno(const Case& C, const Fields<S>& F, const long long* st) {
+  if (C.flags & FORCE_TENO) return true;
+  if (C.flags & FORCE_CENTRAL) return false;
+  double th = 0;
+  for (int m = 0; m < 6; ++m) th = std::max(th, F.theta[st[m]]);
+  double pa = val(F.cell[st[2]].p), pb = val(F.cell[st[3]].p);
+  double psi = std::fabs(pb - pa) / std::min(pa, pb);
+  return (th > C.theta_c) || (psi > C.psi_c);
+}
+
+// Step 3b: convective numerical flux at face i+1/2 along d (all variables);
+// st[0..5] are the linear indices of nodes i-2..i+3.  Returns 1 for TENO.
+template <class S>
+static int conv_flux(const Case& C, const S* U, const Fields<S>& F, int d, const long long* st, S* out) {
+  const long long N = C.N();
+  const int nv = C.ns + 4;
+  bool teno = use_teno(C, F, st);
+  std::vector<S> Uk(nv * 6);
+  for (int m = 0; m < 6; ++m)
+    for (int v = 0; v < nv; ++v) Uk[m * nv + v] = U[v * N + st[m]];
+  if (!teno) {
+    const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+    for (int v = 0; v < nv; ++v) {
+      S s = 0;
+      for (int m = 0; m < 6; ++m) s += cc[m] * node_flux(C, &Uk[m * nv], F.cell[st[m]], v, d);
+      out[v] = s / 60.0;
+    }
+    return 0;
+  }
+  // local Lax-Friedrichs speed: largest |u_n| + c over the stencil (argmax frozen)
+  int am = 0;
+  double best = -1;
+  for (int m = 0; m < 6; ++m) {
+    double sp = std::fabs(val(F.cell[st[m]].u[d])) + val(F.cell[st[m]].c);
+    if (sp > best) { best = sp; am = m; }
+  }
+  S alpha = fabs(F.cell[st[am]].u[d]) + F.cell[st[am]].c;
+  for (int v = 0; v < nv; ++v) {
+    S fp[6], fm[6];
+    for (int m = 0; m < 6; ++m) {
+      S fl = node_flux(C, &Uk[m * nv], F.cell[st[m]], v, d);
+      fp[m] = 0.5 * (fl + alpha * Uk[m * nv + v]);
+      fm[5 - m] = 0.5 * (fl - alpha * Uk[m * nv + v]);   // mirrored: i+3..i-2
+    }
+    out[v] = teno6(fp, C.CT) + teno6(fm, C.CT);
+  }
+  return 1;
+}
+
+// Step 3c: diffusive flux at face i+1/2 along d (eqs. 1-3, 5, 6), sign as it
+// enters the right-hand side.  A second-order compact face form: normal
+// derivatives from the two adjacent nodes, tangential derivatives as the mean
+// of the nodal central differences, face coefficients as arithmetic means.
+template <class S>
+static void diff_flux(const Case& C, const Fields<S>& F, int d, int i, int j, int k, S* out) {
+  const int ns = C.ns;
+  int c0[3] = {i, j, k}, c1[3] = {i, j, k};
+  c1[d] = wrap(c0[d] + 1, C.n[d]);
+  const Cell<S>& A = F.cell[C.idx(c0[0], c0[1], c0[2])];
+  const Cell<S>& B = F.cell[C.idx(c1[0], c1[1], c1[2])];
+  double xf = C.xif[d][c0[d]];
+  // velocity gradient at the face: grad[a][m] = d u_m / d x_a
+  S grad[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int m = 0; m < 3; ++m) grad[a][m] = 0;
+  for (int m = 0; m < 3; ++m) grad[d][m] = xf * (B.u[m] - A.u[m]);
+  for (int a = 0; a < 3; ++a) {
+    if (a == d || C.n[a] == 1) continue;
+    for (int side = 0; side < 2; ++side) {
+      const int* c = side ? c1 : c0;
+      int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+      cp[a] = wrap(c[a] + 1, C.n[a]);
+      cm[a] = wrap(c[a] - 1, C.n[a]);
+      const Cell<S>& zp = F.cell[C.idx(cp[0], cp[1], cp[2])];
+      const Cell<S>& zm = F.cell[C.idx(cm[0], cm[1], cm[2])];
+      for (int m = 0; m < 3; ++m) grad[a][m] += 0.5 * C.xin[a][c[a]] * (zp.u[m] - zm.u[m]) / 2.0;
+    }
+  }
+  S mu = 0.5 * (A.mu + B.mu), lam = 0.5 * (A.lam + B.lam), rho = 0.5 * (A.rho + B.rho);
+  S W = 0.5 * (A.W + B.W);
+  S divu = grad[0][0] + grad[1][1] + grad[2][2];
+  // viscous stress row tau_{d m} (Stokes hypothesis)
+  S tau[3];
+  for (int m = 0; m < 3; ++m) {
+    tau[m] = mu * (grad[d][m] + grad[m][d]);
+    if (m == d) tau[m] -= (2.0 / 3.0) * mu * divu;
+  }
+  // species fluxes J_s = rho Y_s V_s with the correction velocity (sum J_s = 0)
+  std::vector<S> Js(ns), Yf(ns), hf(ns);
+  S corr = 0;
+  for (int s = 0; s < ns; ++s) {
+    S Df = 0.5 * (A.D[s] + B.D[s]);
+    S dX = xf * (B.X[s] - A.X[s]);
+    Js[s] = -rho * Df * (C.W[s] / W) * dX;
+    corr += rho * Df * (C.W[s] / W) * dX;
+    Yf[s] = 0.5 * (A.Y[s] + B.Y[s]);
+    hf[s] = 0.5 * (A.h[s] + B.h[s]);
+  }
+  S qn = -lam * xf * (B.T - A.T);
+  for (int s = 0; s < ns; ++s) {
+    Js[s] += Yf[s] * corr;
+    qn += Js[s] * hf[s];
+  }
+  for (int s = 0; s < ns; ++s) out[s] = -Js[s];
+  S work = 0;
+  for (int m = 0; m < 3; ++m) {
+    out[ns + m] = tau[m];
+    work += tau[m] * 0.5 * (A.u[m] + B.u[m]);
+  }
+  out[ns + 3] = work - qn;
+}
+
+template <class S>
+static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, double t, S* dUdt,
+               S* hrr_out, unsigned char* mask, Fields<S>* keep) {
+  const long long N = C.N();
+  const int ns = C.ns, nv = ns + 4;
+  Fields<S> Floc;
+  Fields<S>& F = keep ? *keep : Floc;
+  int err = eval_cells(C, P, U, T_io, t, F);
+  if (err) return err;
+  for (long long q = 0; q < N * nv; ++q) dUdt[q] = 0;
+  // Step 4 (sources): chemistry into the species equations, laser into energy.
+  for (long long q = 0; q < N; ++q) {
+    if (!(C.flags & CHEM_OFF))
+      for (int s = 0; s < ns; ++s) dUdt[s * N + q] = F.cell[q].wdot[s];
+    dUdt[(ns + 3) * N + q] = F.cell[q].qL;
+    if (hrr_out) hrr_out[q] = F.cell[q].hrr;
+  }
+  for (int d = 0; d < 3; ++d) {
+    if (C.n[d] == 1) continue;
+    // face fluxes, face f = i+1/2 stored at the index of node i
+    std::vector<S> Fc((size_t)N * nv), Fd((size_t)N * nv);
+#pragma omp parallel for schedule(static)
+    for (long long q = 0; q < N; ++q) {
+      int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+      long long st[6];
+      for (int m = 0; m < 6; ++m) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[d] = wrap(c[d] - 2 + m, C.n[d]);
+        st[m] = C.idx(cc[0], cc[1], cc[2]);
+      }
+      std::vector<S> fc(nv), fd(nv);
+      int te = conv_flux(C, U, F, d, st, fc.data());
+      if (mask) mask[(size_t)d * N + q] = (unsigned char)te;
+      if (!(C.flags & VISC_OFF)) diff_flux(C, F, d, c[0], c[1], c[2], fd.data());
+      else for (int v = 0; v < nv; ++v) fd[v] = 0;
+      for (int v = 0; v < nv; ++v) { Fc[(size_t)q * nv + v] = fc[v]; Fd[(size_t)q * nv + v] = fd[v]; }
+    }
+    // flux differences: dU/dt += xi_d (-(Fc_{i+1/2} - Fc_{i-1/2}) + (Fd_{i+1/2} - Fd_{i-1/2}))
+    for (long long q = 0; q < N; ++q) {
+      int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+      int cm[3] = {c[0], c[1], c[2]};
+      cm[d] = wrap(c[d] - 1, C.n[d]);
+      long long qm = C.idx(cm[0], cm[1], cm[2]);
+      double xi = C.xin[d][c[d]];
+      for (int v = 0; v < nv; ++v) {
+        S conv = Fc[(size_t)q * nv + v] - Fc[(size_t)qm * nv + v];
+        S dif = Fd[(size_t)q * nv + v] - Fd[(size_t)qm * nv + v];
+        dUdt[v * N + q] += xi * (dif - conv);
+      }
+    }
+  }
+  return OK;
+}
+
+// Cell volume (product of widths along all three axes).
+static double cell_volume(const Case& C, long long q) {
+  int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+  return 1.0 / (C.xin[0][c[0]] * C.xin[1][c[1]] * C.xin[2][c[2]]);
+}
+
+// Largest stable step: convective and diffusive limits, times the CFL number.
+static int stable_dt(const Case& C, const double* U, double* T_io, double* dt) {
+  Params<double> P;
+  P.lnA.assign(C.lnA.begin(), C.lnA.end());
+  P.E = 0; P.xc[0] = P.xc[1] = P.xc[2] = 0; P.sr = 1; P.t0 = 0; P.st = 1; P.on = false;
+  Fields<double> F;
+  int err = eval_cells(C, P, U, T_io, 0.0, F);
+  if (err) return err;
+  double best = INFINITY;
+  for (long long q = 0; q < C.N(); ++q) {
+    const Cell<double>& z = F.cell[q];
+    int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+    double sc = 0, sd = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (C.n[a] == 1) continue;
+      double xi = C.xin[a][c[a]];
+      sc += (std::fabs(z.u[a]) + z.c) * xi;
+      sd += xi * xi;
+    }
+    double nu = std::max(z.mu / z.rho, z.lam / (z.rho * z.cp));
+    for (int s = 0; s < C.ns; ++s) nu = std::max(nu, z.D[s]);
+    double lim = sc > 0 ? 1.0 / sc : INFINITY;
+    if (!(C.flags & VISC_OFF) && sd > 0) lim = std::min(lim, 1.0 / (2.0 * sd * nu));
+    best = std::min(best, lim);
+  }
+  *dt = C.cfl * best;
+  return OK;
+}
+
+// One SSP-RK3 step (Shu-Osher form) and the step's contribution to the
+// time-integrated heat release, using the scheme's own quadrature weights.
+template <class S>
+static int rk3(const Case& C, const Params<S>& P, S* U, double* T_io, double t, double dt, S* J) {
+  const long long N = C.N();
+  const long long M = N * (C.ns + 4);
+  std::vector<S> U1(M), U2(M), L(M), h(N);
+  const double b[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+  const double tk[3] = {t, t + dt, t + 0.5 * dt};
+  S jstep = 0;
+  for (int stage = 0; stage < 3; ++stage) {
+    const S* Uk = stage == 0 ? U : (stage == 1 ? U1.data() : U2.data());
+    int err = rhs(C, P, Uk, T_io, tk[stage], L.data(), h.data(), (unsigned char*)nullptr, (Fields<S>*)nullptr);
+    if (err) return err;
+    S js = 0;
+    for (long long q = 0; q < N; ++q) js += cell_volume(C, q) * h[q];
+    jstep += b[stage] * js;
+    for (long long q = 0; q < M; ++q) {
+      if (stage == 0) U1[q] = U[q] + dt * L[q];
+      else if (stage == 1) U2[q] = 0.75 * U[q] + 0.25 * (U1[q] + dt * L[q]);
+      else U[q] = (1.0 / 3.0) * U[q] + (2.0 / 3.0) * (U2[q] + dt * L[q]);
+    }
+  }
+  if (J) *J += dt * jstep;
+  return OK;
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+// ---------------------------------------------------------------- C entry points
+extern "C" {
+
+void* orc_case_new(int ns, int nr, const double* W, const double* a7, const double* sig, const double* epsk,
+                   const double* lnA, const double* beta, const double* Ea, const int* nuf, const int* nur,
+                   double Tmin, double Tmax, const int* n, const double* xnode, const double* xin,
+                   const double* xif, const double* L, double theta_c, double psi_c, double CT, double cfl,
+                   unsigned flags) {
+  Case* C = new Case();
+  C->ns = ns; C->nr = nr;
+  C->W.assign(W, W + ns);
+  C->a7.assign(a7, a7 + 7 * ns);
+  C->sig.assign(sig, sig + ns);
+  C->epsk.assign(epsk, epsk + ns);
+  C->lnA.assign(lnA, lnA + nr);
+  C->beta.assign(beta, beta + nr);
+  C->Ea.assign(Ea, Ea + nr);
+  C->nuf.assign(nuf, nuf + nr * ns);
+  C->nur.assign(nur, nur + nr * ns);
+  C->Tmin = Tmin; C->Tmax = Tmax;
+  long long off = 0;
+  for (int a = 0; a < 3; ++a) {
+    C->n[a] = n[a];
+    C->xnode[a].assign(xnode + off, xnode + off + n[a]);
+    C->xin[a].assign(xin + off, xin + off + n[a]);
+    C->xif[a].assign(xif + off, xif + off + n[a]);
+    C->L[a] = L[a];
+    off += n[a];
+  }
+  C->theta_c = theta_c; C->psi_c = psi_c; C->CT = CT; C->cfl = cfl; C->flags = flags;
+  return C;
+}
+
+void orc_case_free(void* h) { delete (Case*)h; }
+
+void orc_set_flags(void* h, unsigned flags) { ((Case*)h)->flags = flags; }
+
+static Params<double> make_params(const Case& C, const double* las, const double* lnA) {
+  Params<double> P;
+  P.lnA.assign(lnA ? lnA : C.lnA.data(), (lnA ? lnA : C.lnA.data()) + C.nr);
+  P.E = las[0]; P.xc[0] = las[1]; P.xc[1] = las[2]; P.xc[2] = las[3];
+  P.sr = las[4]; P.t0 = las[5]; P.st = las[6]; P.on = las[7] != 0.0;
+  return P;
+}
+
+// Conserved state from primitives (Y_s, T, p, u): rho from eq. (4); total
+// energy includes the species enthalpies of formation.
+int orc_prim_to_cons(void* h, const double* Y, const double* T, const double* p, const double* vel, double* U) {
+  const Case& C = *(Case*)h;
+  const long long N = C.N();
+  const int ns = C.ns;
+  for (long long q = 0; q < N; ++q) {
+    double iW = 0;
+    for (int s = 0; s < ns; ++s) iW += Y[s * N + q] / C.W[s];
+    double rho = p[q] / (Ru * T[q] * iW);
+    double hm = 0;
+    for (int s = 0; s < ns; ++s) hm += Y[s * N + q] * (Ru / C.W[s]) * T[q] * h_RT(&C.a7[7 * s], T[q]);
+    double ke = 0;
+    for (int m = 0; m < 3; ++m) {
+      U[(ns + m) * N + q] = rho * vel[m * N + q];
+      ke += vel[m * N + q] * vel[m * N + q];
+    }
+    for (int s = 0; s < ns; ++s) U[s * N + q] = rho * Y[s * N + q];
+    U[(ns + 3) * N + q] = rho * hm - p[q] + 0.5 * rho * ke;
+  }
+  return OK;
+}
+
+// Per-cell quantities, for per-step comparisons.  out layout [nq][N] with
+// rows: T, p, c, mu, lambda, D_s (ns), wdot_s (ns), hrr, q_L, theta.
+int orc_cells(void* h, const double* U, double* T_io, double t, const double* las, double* out) {
+  const Case& C = *(Case*)h;
+  Params<double> P = make_params(C, las, nullptr);
+  Fields<double> F;
+  int err = eval_cells(C, P, U, T_io, t, F);
+  if (err) return err;
+  const long long N = C.N();
+  const int ns = C.ns;
+  for (long long q = 0; q < N; ++q) {
+    const Cell<double>& z = F.cell[q];
+    int r = 0;
+    out[(r++) * N + q] = z.T;
+    out[(r++) * N + q] = z.p;
+    out[(r++) * N + q] = z.c;
+    out[(r++) * N + q] = z.mu;
+    out[(r++) * N + q] = z.lam;
+    for (int s = 0; s < ns; ++s) out[(r++) * N + q] = z.D[s];
+    for (int s = 0; s < ns; ++s) out[(r++) * N + q] = (C.flags & CHEM_OFF) ? 0.0 : z.wdot[s];
+    out[(r++) * N + q] = z.hrr;
+    out[(r++) * N + q] = z.qL;
+    out[(r++) * N + q] = F.theta[q];
+  }
+  return OK;
+}
+
+int orc_rhs(void* h, const double* U, double* T_io, double t, const double* las, double* dUdt, double* hrr,
+            unsigned char* mask) {
+  const Case& C = *(Case*)h;
+  Params<double> P = make_params(C, las, nullptr);
+  return rhs(C, P, U, T_io, t, dUdt, hrr, mask, (Fields<double>*)nullptr);
+}
+
+int orc_stable_dt(void* h, const double* U, double* T_io, double* dt) {
+  return stable_dt(*(Case*)h, U, T_io, dt);
+}
+
+int orc_rk3_step(void* h, double* U, double* T_io, double t, double dt, const double* las, const double* lnA,
+                 double* J) {
+  const Case& C = *(Case*)h;
+  Params<double> P = make_params(C, las, lnA);
+  return rk3(C, P, U, T_io, t, dt, J);
+}
+
+// Forward-mode tangent of one RK3 step: (U, dU) -> (U', dU'), and (J, dJ),
+// for parameter tangents dlas = (dE, dxc, dyc, dzc) and dlnA.
+int orc_rk3_tangent(void* h, double* U, double* dU, double* T_io, double t, double dt, const double* las,
+                    const double* dlas, const double* lnA, const double* dlnA, double* J, double* dJ) {
+  const Case& C = *(Case*)h;
+  const long long M = C.N() * (C.ns + 4);
+  Params<Dual> P;
+  P.lnA.resize(C.nr);
+  for (int j = 0; j < C.nr; ++j) P.lnA[j] = Dual(lnA ? lnA[j] : C.lnA[j], dlnA ? dlnA[j] : 0.0);
+  P.E = Dual(las[0], dlas[0]);
+  for (int a = 0; a < 3; ++a) P.xc[a] = Dual(las[1 + a], dlas[1 + a]);
+  P.sr = las[4]; P.t0 = las[5]; P.st = las[6]; P.on = las[7] != 0.0;
+  std::vector<Dual> Ud(M);
+  for (long long q = 0; q < M; ++q) Ud[q] = Dual(U[q], dU[q]);
+  Dual Jd(J ? *J : 0.0, dJ ? *dJ : 0.0);
+  int err = rk3(C, P, Ud.data(), T_io, t, dt, &Jd);
+  if (err) return err;
+  for (long long q = 0; q < M; ++q) { U[q] = Ud[q].v; dU[q] = Ud[q].d; }
+  if (J) *J = Jd.v;
+  if (dJ) *dJ = Jd.d;
+  return OK;
+}
+
+// Tangent of one RHS evaluation (state and parameter directions).
+int orc_rhs_tangent(void* h, const double* U, const double* dU, double* T_io, double t, const double* las,
+                    const double* dlas, const double* dlnA, double* dUdt, double* ddUdt, double* hrr,
+                    double* dhrr) {
+  const Case& C = *(Case*)h;
+  const long long N = C.N();
+  const long long M = N * (C.ns + 4);
+  Params<Dual> P;
+  P.lnA.resize(C.nr);
+  for (int j = 0; j < C.nr; ++j) P.lnA[j] = Dual(C.lnA[j], dlnA ? dlnA[j] : 0.0);
+  P.E = Dual(las[0], dlas[0]);
+  for (int a = 0; a < 3; ++a) P.xc[a] = Dual(las[1 + a], dlas[1 + a]);
+  P.sr = las[4]; P.t0 = las[5]; P.st = las[6]; P.on = las[7] != 0.0;
+  std::vector<Dual> Ud(M), L(M), hd(N);
+  for (long long q = 0; q < M; ++q) Ud[q] = Dual(U[q], dU[q]);
+  int err = rhs(C, P, Ud.data(), T_io, t, L.data(), hd.data(), (unsigned char*)nullptr, (Fields<Dual>*)nullptr);
+  if (err) return err;
+  for (long long q = 0; q < M; ++q) { dUdt[q] = L[q].v; ddUdt[q] = L[q].d; }
+  for (long long q = 0; q < N; ++q) {
+    if (hrr) hrr[q] = hd[q].v;
+    if (dhrr) dhrr[q] = hd[q].d;
+  }
+  return OK;
+}
+
+// Building blocks exposed for the pins.
+double orc_teno6(const double* f, double CT) { return teno6(f, CT); }
+// beta0..beta3, beta6, tau, chi0..chi3, omega0..omega3
+double orc_teno6_detail(const double* f, double CT, double* detail) { return teno6(f, CT, detail); }
+// c_p/R, h/(RT), s/R of species s at temperature T
+void orc_thermo(void* h, int s, double T, double* out) {
+  const Case& C = *(Case*)h;
+  const double* a = &C.a7[7 * s];
+  out[0] = cp_R(a, T);
+  out[1] = h_RT(a, T);
+  out[2] = s_R(a, T);
+}
+double orc_omega22(double Ts) { return omega22(Ts); }
+double orc_omega11(double Ts) { return omega11(Ts); }
+double orc_mu_species(void* h, int s, double T) { return mu_species(*(Case*)h, s, T); }
+double orc_D_binary(void* h, int i, int j, double T, double p) { return D_binary(*(Case*)h, i, j, T, p); }
+double orc_cell_volume(void* h, long long q) { return cell_volume(*(Case*)h, q); }
+
+// Forward and backward rates of progress (mol m^-3 s^-1) of every reaction
+// in every cell: out[(2 j + {0,1}) N + q].
+int orc_rates(void* h, const double* U, double* T_io, double* out) {
+  const Case& C = *(Case*)h;
+  const long long N = C.N();
+  const int nv = C.ns + 4;
+  Params<double> P;
+  P.lnA.assign(C.lnA.begin(), C.lnA.end());
+  P.E = 0; P.xc[0] = P.xc[1] = P.xc[2] = 0; P.sr = 1; P.t0 = 0; P.st = 1; P.on = false;
+  std::vector<double> r(2 * C.nr + 2);
+  for (long long q = 0; q < N; ++q) {
+    std::vector<double> Uc(nv);
+    for (int v = 0; v < nv; ++v) Uc[v] = U[v * N + q];
+    Cell<double> z;
+    int e = primitives(C, Uc.data(), T_io[q], z);
+    if (e) return e;
+    T_io[q] = z.T;
+    chemistry(C, P, Uc.data(), z, r.data());
+    for (int k = 0; k < 2 * C.nr; ++k) out[k * N + q] = r[k];
+  }
+  return OK;
+}
+
+}  // extern "C"
