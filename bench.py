@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput of the reacting-flow RK3 step on one MI355X.
+
+A step is one SSP-RK3 step of the full hot path on the 128^3 periodic
+multicomponent Taylor-Green box (9 species, 20 reversible reactions,
+mixture-averaged transport, Mach 0.3): per stage the per-cell kernel
+(primitives, Newton T, transport, chemistry, source, heat release; the first
+stage also reduces the stable dt), the dilatation sensor, and the fused flux
+sweep with the stage update; the time-integrated heat release accumulates on
+the device.  Inputs are seeded synthetic fields resident in HBM.
+
+Prints one JSON line.  `value` = cells x 3 stages x steps / time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
+EXP_WEIGHT = 20                # FP64 operations charged per exp/log (polynomial evaluation)
+
+
+def point_flops_per_cell(ns, nr, laser_on, newton_iters=3):
+    """Algorithmic FP64 operations of the per-cell kernel (one stage), from
+    the operation counts of its formulas; each exp/log counts EXP_WEIGHT."""
+    newton = newton_iters * (ns * 25 + 2)
+    thermo = ns * 13 + ns * 2 + 8
+    transport = ns * 20 + ns * ns * 6 + ns * 5 + (ns * (ns - 1) // 2) * 17 + ns * 2
+    trans_exp = 3 * ns + 4 * (ns * (ns - 1) // 2) + 2
+    chem = ns * 21 + nr * (5 + 2 * ns + 2 + 4 + 1 + 2 * ns) + ns * 14
+    chem_exp = 2 * nr + 1
+    laser = 30 if laser_on else 0
+    laser_exp = 9 if laser_on else 0
+    misc = 40
+    return newton + thermo + transport + chem + laser + misc + EXP_WEIGHT * (trans_exp + chem_exp + laser_exp)
+
+
+def sweep_bytes_per_cell(ns):
+    """Algorithmic HBM bytes of the fused sweep per cell and stage: read U,
+    T, the per-cell fields (p, c, mu, lambda, u, v, w, D_s), the sources
+    (wdot_s, q_L), the sensor byte and (stages 2-3) U^n; write the stage."""
+    nv = ns + 4
+    reads = 8 * (nv + 1 + (7 + ns) + (ns + 1)) + 1 + 8 * nv * 2.0 / 3.0
+    return reads + 8 * nv
+
+
+def point_bytes_per_cell(ns):
+    nv = ns + 4
+    return 8 * (nv + 1) + 8 * (1 + (7 + ns) + (ns + 1))
+
+
+def cpu_baseline(case, seconds_target=15.0):
+    """The oracle (test infrastructure) timed on the host cores on a bounded
+    sample of the same workload: one full right-hand-side evaluation (one
+    stage) of the whole grid, or of a leading slab if that is too long."""
+    import numpy as np
+    from oracle import Oracle
+    import synth
+    nz = case.grid.n[2]
+    t_probe = None
+    sub = case
+    for kz in (4, nz):
+        n = (case.grid.n[0], case.grid.n[1], min(kz, nz))
+        g = synth.Grid(n=n, xnode=[case.grid.xnode[0], case.grid.xnode[1], case.grid.xnode[2][:n[2]]],
+                       xin=[case.grid.xin[0], case.grid.xin[1], case.grid.xin[2][:n[2]]],
+                       xif=[case.grid.xif[0], case.grid.xif[1], case.grid.xif[2][:n[2]]], L=case.grid.L)
+        N = g.N
+        sub = synth.Case(case.name, case.mech, g, case.Y[:, :N], case.T[:N], case.p[:N], case.vel[:, :N],
+                         laser=case.laser, flags=case.flags)
+        o = Oracle(sub)
+        U = o.prim_to_cons()
+        T = sub.T.copy()
+        t0 = time.perf_counter()
+        o.rhs(U, T, t=0.0)
+        el = time.perf_counter() - t0
+        if t_probe is None:
+            t_probe = el
+            if el * nz / kz > 2 * seconds_target:
+                break
+        else:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sub.grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one RHS evaluation (one stage) of a {sub.grid.n[0]}x{sub.grid.n[1]}x{sub.grid.n[2]} "
+                      f"slab of the workload, {el:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["tgv128", "mixing256"], default="tgv128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (ensemble members or grid blocks "
+              "would shard across GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2202_02319_amd import htr
+
+    case = synth.case_c2() if args.workload == "tgv128" else synth.case_c3()
+    ctx = htr.Context.from_case(case)
+    N = ctx.N
+    U = htr.cons_from_case(ctx, case)
+    T = htr.to_dev(case.T)
+    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    J_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    work = ctx.new_work()
+    laser = case.laser if case.laser.on else None
+
+    def step():
+        htr.htr_rk3_step(ctx, U, T, t_dev, dt_dev, 1, laser, None, work, J_dev)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    htr.htr_check(ctx)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    htr.htr_check(ctx)
+    ms = e0.elapsed_time(e1) / args.steps
+    value = N * 3 * args.steps / (ms * args.steps / 1e3)
+
+    # per-kernel durations, HIP events on the launch stream, same steps again
+    htr.htr_timing(ctx, 1)
+    for _ in range(args.steps):
+        step()
+    kt = htr.htr_timing_read(ctx)
+    htr.htr_timing(ctx, 0)
+    htr.htr_check(ctx)
+    ns, nr = case.mech.ns, case.mech.nr
+    avg = {k: (v[0] / max(v[1], 1), v[1]) for k, v in kt.items()}
+    dom = max(("point", "sweep"), key=lambda k: kt[k][0])
+    if dom == "sweep":
+        traffic_b = sweep_bytes_per_cell(ns) * N
+        ach = traffic_b / (avg["sweep"][0] / 1e3) / 1e9
+        roof = {"kernel": "k_sweep", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        fl = point_flops_per_cell(ns, nr, laser is not None) * N
+        ach = fl / (avg["point"][0] / 1e3) / 1e12
+        roof = {"kernel": "k_point", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof["kernel_ms"] = {k: round(v[0], 4) for k, v in avg.items()}
+    roof["step_ms_by_kernel"] = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
+
+    out = {
+        "metric": "FP64 cell-stage updates/s (plain vs batched ensemble); adjoint/forward time",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_s": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D periodic multicomponent Taylor-Green box 128^3, 9 species, 20 reactions, "
+                               "Mach 0.3, SSP-RK3 with in-step CFL dt"
+                   if args.workload == "tgv128" else
+                   "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser",
+                   "cells": N, "species": ns, "reactions": nr, "stages_per_step": 3},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * htr.h -- C interface of the MI355X (gfx950) library for the explicit
+ * right-hand side of the compressible multicomponent reacting Navier-Stokes
+ * equations on structured periodic grids, and its SSP-RK3 time step.
+ *
+ * Paper: Maeda et al., "An integrated heterogeneous computing framework for
+ * ensemble simulations of laser-induced ignition", arXiv 2202.02319.
+ *   - conserved state, fluxes, sources: Sec. 5.1, eqs. (1)-(3); closure eq. (4)
+ *   - transport: Wilke viscosity, heat flux eq. (5), diffusion velocity
+ *     eq. (6) with mixture-averaged (Bird) and binary (Hirschfelder) D
+ *   - chemistry: finite-rate reversible Arrhenius reactions (Sec. 5.1,
+ *     "Combustion chemistry")
+ *   - discretisation: conservative finite differences with TENO6 / central
+ *     convective fluxes, second-order central diffusive fluxes, SSP-RK3
+ *     (Sec. 5.2, "Numerical method"); grid metrics of the mapped equations
+ *     (Sec. 5.2) in their rectilinear form
+ *   - laser energy source q_L: Sec. 6.3.1, eq. (laser-qs)
+ *
+ * Conventions shared by every entry point
+ *   - Units are SI.  All floating-point data are IEEE double.
+ *   - A state U is stored variable-major: U[v][k][j][i] with i fastest,
+ *     v = 0..ns-1 the partial densities rho*Y_s, then rho*u, rho*v, rho*w,
+ *     then the total energy E (which includes the species enthalpies of
+ *     formation).  nv = ns + 4.  N = nx*ny*nz cells.
+ *   - Every pointer named *_dev, and every state / field pointer of the
+ *     compute calls (U, T_io, dUdt, work, ...), is DEVICE memory on the
+ *     device current at htr_create; descriptor pointers of htr_create are
+ *     HOST memory and are copied.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Compute calls are asynchronous: they validate their
+ *     arguments synchronously (returning HTR_EINVAL before any launch) and
+ *     then only enqueue work.  They never allocate device memory.
+ *   - Device-side numerical failures (non-finite state, rho <= 0, Newton
+ *     not converged, T outside [Tmin, Tmax]) are latched in a status word
+ *     owned by the context and reported by htr_check.
+ *   - The library never throws across this interface and never exits.
+ *   - Boundaries are periodic in every direction; an axis with n = 1 is
+ *     inactive (no flux), which gives 1-D and 2-D problems.
+ *   - Calls on one context that overlap in time (different streams without
+ *     ordering) race on the context's internal buffers.
+ */
+#ifndef HTR_H
+#define HTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HTR_OK = 0,
+  HTR_EINVAL = 1,        /* bad argument (null, size, range)                 */
+  HTR_ENOMEM = 2,        /* device allocation failed (htr_create only)       */
+  HTR_EDEVICE = 3,       /* HIP runtime error                                */
+  HTR_ENONFINITE = 4,    /* non-finite state or rho <= 0 met on the device   */
+  HTR_ENEWTON = 5,       /* temperature Newton iteration did not converge    */
+  HTR_ETRANGE = 6,       /* temperature left [Tmin, Tmax]                    */
+  HTR_EUNSUPPORTED = 7   /* valid but not supported (e.g. ns > HTR_MAX_NS)   */
+} htr_status;
+
+#define HTR_MAX_NS 12          /* species per mechanism                      */
+#define HTR_MAX_NR 64          /* reactions per mechanism                    */
+#define HTR_MAX_SIDE 3         /* distinct species on one side of a reaction */
+
+/* scheme flags */
+#define HTR_CHEM_OFF      1u   /* no chemical source (the paper's inert stage, Sec. 6.4.1) */
+#define HTR_VISC_OFF      2u   /* no diffusive fluxes                                      */
+#define HTR_FORCE_CENTRAL 4u   /* central flux on every face                               */
+#define HTR_FORCE_TENO    8u   /* TENO6 on every face                                      */
+
+typedef struct htr_ctx htr_ctx;
+typedef struct htr_batch htr_batch;
+
+/* Mechanism tables (HOST pointers, copied by htr_create).  Sec. 5.1. */
+typedef struct {
+  int32_t ns, nr;
+  const double* W;          /* [ns] molar masses, kg/mol                           */
+  const double* nasa7;      /* [ns][7] NASA 7-coefficient polynomial, one range    */
+  const double* lj_sigma;   /* [ns] Lennard-Jones diameter, m                       */
+  const double* lj_epsk;    /* [ns] Lennard-Jones well depth over k_B, K            */
+  const double* lnA;        /* [nr] ln of the SI pre-exponential factor             */
+  const double* beta;       /* [nr] temperature exponent                            */
+  const double* Ea;         /* [nr] activation energy, J/mol                        */
+  const int32_t* nu_f;      /* [nr][ns] reactant stoichiometric coefficients        */
+  const int32_t* nu_r;      /* [nr][ns] product stoichiometric coefficients         */
+  double Tmin, Tmax;        /* validity range of the polynomials, K                 */
+} htr_mech_desc;
+
+/* Rectilinear periodic grid (HOST pointers, copied).  For axis a:
+ * xnode[a][i] node coordinate, xi_node[a][i] = d(xi)/dx at node i,
+ * xi_face[a][i] = d(xi)/dx at face i+1/2, L[a] the period.  A uniform grid
+ * has xi_node = xi_face = 1/dx.  For an inactive axis (n = 1) xi_node[0] is
+ * 1/width (it enters the cell volume only). */
+typedef struct {
+  int32_t n[3];
+  const double* xnode[3];
+  const double* xi_node[3];
+  const double* xi_face[3];
+  double L[3];
+} htr_grid_desc;
+
+/* Gaussian laser kernel, eq. (laser-qs), generalised to d active axes:
+ * q_L = E / ((2 pi)^((d+1)/2) sigma_r^d sigma_t) * prod_a G_a(x_a)
+ *       * exp(-(t - t0)^2 / (2 sigma_t^2)),
+ * G_a the Gaussian of width sigma_r wrapped over the periodic images. */
+typedef struct {
+  double E;
+  double center[3];
+  double sigma_r;
+  double t0;
+  double sigma_t;
+  int32_t on;
+} htr_laser;
+
+typedef struct {
+  double cfl;        /* CFL number of htr_stable_dt                       */
+  double theta_c;    /* dilatation sensor threshold of the hybrid switch  */
+  double psi_c;      /* relative pressure-jump threshold                  */
+  double teno_CT;    /* TENO cut-off C_T                                  */
+  uint32_t flags;    /* HTR_* scheme flags                                */
+} htr_scheme;
+
+/* Create a context for one mechanism, one grid and one scheme on the current
+ * device; allocates the context's device tables and scratch.  *out is NULL on
+ * failure.  Errors: HTR_EINVAL (null pointer, n < 1, ns < 1, metric <= 0,
+ * bad stoichiometry), HTR_EUNSUPPORTED (ns > HTR_MAX_NS, nr > HTR_MAX_NR,
+ * more than HTR_MAX_SIDE species or total order > 3 on a reaction side),
+ * HTR_ENOMEM, HTR_EDEVICE. */
+htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, const htr_scheme* scheme,
+                      htr_ctx** out);
+/* Waits for the context's streams to drain and frees it.  NULL is HTR_EINVAL. */
+htr_status htr_destroy(htr_ctx* ctx);
+/* Replace the scheme flags of an existing context. */
+htr_status htr_set_flags(htr_ctx* ctx, uint32_t flags);
+/* Number of cells of the context's grid (0 for NULL). */
+int64_t htr_num_cells(const htr_ctx* ctx);
+
+/* Conserved state from primitive fields (eq. 4 for rho; E includes the
+ * formation enthalpies): Y[ns][N], T[N], p[N], vel[3][N] -> U[nv][N]. */
+htr_status htr_prim_to_cons(htr_ctx* ctx, const double* Y, const double* T, const double* p,
+                            const double* vel, double* U, void* stream);
+
+/* One right-hand side evaluation dUdt = L(U, t) (eqs. 1-3 in the mapped
+ * conservative form of Sec. 5.2): hybrid TENO6/central convective fluxes,
+ * second-order diffusive fluxes, chemistry and laser sources.
+ *   U      [nv][N] in
+ *   T_io   [N] in/out: Newton starting guess in, converged T out
+ *   dUdt   [nv][N] out
+ *   hrr    [N] out, nullable: heat-release rate -sum_s h_s wdot_s (W/m^3)
+ *   laser  HOST pointer, nullable (no laser) */
+htr_status htr_rhs(htr_ctx* ctx, const double* U, double* T_io, double t, const htr_laser* laser, double* dUdt,
+                   double* hrr, void* stream);
+
+/* Per-cell derived quantities of the right-hand side, for inspection:
+ * out[nq][N] with rows T, p, c, mu, lambda, D_s (ns rows), wdot_s (ns rows),
+ * hrr, q_L, theta (the dilatation sensor); nq = 5 + 2 ns + 3. */
+htr_status htr_cells(htr_ctx* ctx, const double* U, double* T_io, double t, const htr_laser* laser,
+                     double* out, void* stream);
+
+/* Stable step: dt = cfl * min over cells of the convective limit
+ * 1 / sum_d (|u_d| + c) xi_d and, unless HTR_VISC_OFF, the diffusive limit
+ * 1 / (2 sum_d xi_d^2 max(mu/rho, lambda/(rho c_p), max_s D_s)).
+ * Writes one double to dt_dev (device). */
+htr_status htr_stable_dt(htr_ctx* ctx, const double* U, double* T_io, double* dt_dev, void* stream);
+
+/* Bytes of caller-owned work memory htr_rk3_step needs (two stage states). */
+size_t htr_work_bytes(const htr_ctx* ctx);
+
+/* One SSP-RK3 step in Shu-Osher form (Gottlieb et al. 2001, Sec. 5.2):
+ *   U1 = U + dt L(U, t); U2 = 3/4 U + 1/4 (U1 + dt L(U1, t+dt));
+ *   U <- 1/3 U + 2/3 (U2 + dt L(U2, t+dt/2)).
+ *   U          [nv][N] in/out (device)
+ *   T_io       [N] in/out Newton guess cache (holds T of the last stage)
+ *   t_dev      device double in/out: the time, advanced by dt at the end
+ *   dt_dev     device double: the step; read, or, when compute_dt != 0,
+ *              written first with the htr_stable_dt value of U (computed in
+ *              the first stage's per-cell kernel, no extra pass)
+ *   dlnA_dev   nullable device [nr]: offsets added to ln A for this call
+ *   work       device, >= htr_work_bytes(ctx)
+ *   J_dev      nullable device double: J += dt sum_k b_k sum_cells dV hrr(U^(k), t_k)
+ *              with b = (1/6, 1/6, 2/3): the time-integrated heat release.
+ * The host never waits inside a step. */
+htr_status htr_rk3_step(htr_ctx* ctx, double* U, double* T_io, double* t_dev, double* dt_dev, int compute_dt,
+                        const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
+                        void* stream);
+
+/* Kernel timing for diagnostics: while enabled, every kernel the context
+ * launches is bracketed by HIP events on its stream.  htr_timing_read
+ * synchronises and returns, per kernel class (0 point, 1 sensor, 2 sweep,
+ * 3 reductions and small kernels), the summed milliseconds and launch
+ * counts since htr_timing(ctx, 1).  ms and launches are HOST arrays of 4. */
+htr_status htr_timing(htr_ctx* ctx, int enable);
+htr_status htr_timing_read(htr_ctx* ctx, double* ms, int64_t* launches);
+
+/* Synchronises `stream`, returns the first device-side error latched since
+ * the last htr_check (and clears it), or HTR_EDEVICE for a HIP error. */
+htr_status htr_check(htr_ctx* ctx, void* stream);
+
+/* Message of the last error returned on the calling thread. */
+const char* htr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTR_H */

@@ -1,0 +1,117 @@
+// Device-side data structures shared by the HIP kernels and the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "htr.h"
+
+namespace htr {
+
+constexpr int MAXNS = HTR_MAX_NS;
+constexpr int MAXNR = HTR_MAX_NR;
+constexpr int SIDE = HTR_MAX_SIDE;
+constexpr int BLK = 256;            // threads per block of the per-cell kernels
+
+// exact SI constants
+constexpr double KB = 1.380649e-23;
+constexpr double NAV = 6.02214076e23;
+constexpr double RU = 8.31446261815324;
+constexpr double PREF = 101325.0;   // standard-state pressure of K_c
+constexpr double PI = 3.14159265358979323846;
+
+// device status bits (first error wins by priority in htr_check)
+constexpr unsigned ST_NONFINITE = 1u, ST_NEWTON = 2u, ST_TRANGE = 4u;
+
+// Mechanism tables, precomputed on the host in the forms the kernels use.
+struct MechTables {
+  int ns, nr;
+  double Tmin, Tmax;
+  double W[MAXNS], iW[MAXNS], RW[MAXNS];   // W, 1/W, R_u/W
+  double cp[MAXNS][5];                     // c_p/R = sum_k cp[k] T^k
+  double hc[MAXNS][6];                     // h/(RT) = sum_{k<5} hc[k] T^k + hc[5]/T
+  double sc[MAXNS][6];                     // s/R = sc[0] ln T + sum_{k=1..4} sc[k] T^k + sc[5]
+  double mu_pre[MAXNS];                    // mu_s = mu_pre sqrt(T) / Omega22(T/eps)
+  double ieps[MAXNS], lneps[MAXNS];        // 1/(eps/k), ln(eps/k)
+  double euck[MAXNS];                      // (5/4) R_u / W
+  double wq[MAXNS][MAXNS];                 // (W_j / W_i)^(1/4)
+  double wp[MAXNS][MAXNS];                 // 1 / sqrt(8 (1 + W_i / W_j))
+  double Dpre[MAXNS][MAXNS];               // D_ij = Dpre T^(3/2) / (p Omega11(T/eps_ij))
+  double Dieps[MAXNS][MAXNS], Dlneps[MAXNS][MAXNS];
+  double lnA[MAXNR], beta[MAXNR], EaR[MAXNR], dnu[MAXNR];
+  double nunet[MAXNR][MAXNS];              // nu'' - nu'
+  int nre[MAXNR], npr[MAXNR];              // distinct reactant / product species
+  int ridx[MAXNR][SIDE], rnu[MAXNR][SIDE];
+  int pidx[MAXNR][SIDE], pnu[MAXNR][SIDE];
+};
+
+struct LaserDev {
+  double E, xc[3], sr, t0, st;
+  double norm;     // 1 / ((2 pi)^((d+1)/2) sr^d st)
+  int M[3];        // periodic images summed per axis
+  int on;
+};
+
+// One grid (an ensemble member, or the single grid of a context).  Field
+// arrays of all members are packed: member m's block of a [rows][N_m] field
+// starts at base + rows * off.
+struct Member {
+  int n[3];
+  int act[3];                 // n[a] > 1
+  long long N;
+  long long off;              // cell offset in packed arrays
+  int block_begin;            // first block of this member in per-cell launches
+  int nblocks;
+  const double* xin[3];       // d(xi)/dx at nodes
+  const double* xif[3];       // d(xi)/dx at faces i+1/2
+  const double* xnode[3];     // node coordinates
+  double L[3];
+  LaserDev laser;
+  const double* dlnA;         // nullable [nr]
+};
+
+// Per-call overrides used by the single-grid entry points.
+struct CallArgs {
+  double t;                   // time of stage 0 (when t_dev is null)
+  const double* t_dev;        // nullable [nmem]: per-member time
+  const double* dt_dev;       // nullable [nmem]: per-member step
+  double tcoef;               // stage time = t + tcoef * dt
+  LaserDev laser;             // used when use_call_laser
+  int use_call_laser;
+  const double* dlnA;         // nullable: overrides member dlnA
+  unsigned flags;
+};
+
+__device__ __forceinline__ int find_member(const Member* __restrict__ mem, int nmem, int b) {
+  int lo = 0, hi = nmem - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (mem[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i = i % n;
+  return i < 0 ? i + n : i;
+}
+
+// host-side launchers (defined in the .hip files)
+struct Workspace;
+hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
+                               const double* Y, const double* T, const double* p, const double* vel, double* U,
+                               hipStream_t s);
+hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                        const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
+                        double* cells_out, unsigned* status, int want_dt, hipStream_t s);
+hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
+                         double theta_c, double* theta_out, hipStream_t s);
+hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                        const double* U, const double* Un, const double* T, const double* aux, const double* src,
+                        const unsigned char* flag, double* out, double ca, double cb, int rhs_only,
+                        double psi_c, double CT, hipStream_t s);
+hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
+                           double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
+hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);
+
+}  // namespace htr

@@ -1,0 +1,72 @@
+// Host-side internals shared by the C interface files.
+#pragma once
+
+#include <cstdarg>
+#include <vector>
+
+#include "htr.h"
+#include "htr_dev.h"
+
+namespace htr {
+
+// Scratch owned by a context or an ensemble: per-cell derived fields,
+// sources, sensor flags, block partials, status word.
+struct Workspace {
+  int ns = 0;
+  long long N = 0;
+  double* aux = nullptr;          // [7 + ns][N]
+  double* src = nullptr;          // [ns + 1][N]
+  unsigned char* flag = nullptr;  // [N]
+  double* blkred = nullptr;       // [2][nblocks]
+  unsigned* status = nullptr;
+  double* scal = nullptr;         // [2][nmem] scratch scalars
+};
+
+// HIP-event kernel timer (diagnostics).
+struct Timer {
+  bool on = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void clear();
+  ~Timer();
+};
+
+// Brackets one launch with events when the timer is on.
+struct TimedLaunch {
+  Timer* t;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  TimedLaunch(Timer* t_, int cls_, hipStream_t s_);
+  ~TimedLaunch();
+};
+
+// What a kernel sequence needs to know about the grids it runs on.
+struct Ctx {
+  int ns = 0;
+  const MechTables* M = nullptr;
+  const Member* mem = nullptr;
+  int nmem = 1;
+  int nblocks = 0;
+  htr_scheme scheme{};
+  long long total_cells = 0;
+  int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
+  double L1[3] = {1, 1, 1};
+  Timer* timer = nullptr;
+};
+
+LaserDev make_laser(const htr_laser* L, const int n[3], const double Lp[3]);
+htr_status check_laser(const htr_laser* L);
+htr_status build_tables(const htr_mech_desc* m, MechTables* T);
+htr_status ws_alloc(Workspace& w, int ns, long long N, int nblocks, int nmem);
+void ws_free(Workspace& w);
+htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const double* U, const double* Un, double* T,
+                 double* out, double ca, double cb, int rhs_only, double* hrr, double* J_dev, double jcoef,
+                 hipStream_t s, int want_dt, double* dt_out);
+htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t_dev, double* dt_dev,
+               int compute_dt, const htr_laser* laser, const double* dlnA, double* work, double* J_dev,
+               hipStream_t s);
+
+}  // namespace htr

@@ -1,0 +1,491 @@
+// Per-cell kernels: conserved state from primitives, and the point kernel
+// (primitives with Newton for T, mixture-averaged transport, finite-rate
+// chemistry, laser source, heat release, stable-step limit), plus the
+// dilatation sensor and the per-member reductions.
+//
+// Paper (arXiv 2202.02319) Sec. 5.1: eqs. (1)-(4), Wilke viscosity, NASA
+// thermodynamics, heat flux eq. (5), diffusion velocity eq. (6) with Bird
+// mixture-averaged and Hirschfelder binary diffusivities, Arrhenius
+// chemistry; Sec. 6.3.1 eq. (laser-qs) for q_L.
+//
+// One thread per cell.  The species count is a compile-time parameter so
+// that every per-species array lives in registers; species concentrations
+// used by the mass-action products (indexed by a reaction's species list)
+// are staged in LDS, one column per thread.
+
+#include <math.h>
+
+#include "htr_dev.h"
+
+namespace htr {
+
+__device__ __forceinline__ double cpR(const MechTables* __restrict__ M, int s, double T) {
+  const double* a = M->cp[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+}
+__device__ __forceinline__ double hRT(const MechTables* __restrict__ M, int s, double T, double iT) {
+  const double* a = M->hc[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5] * iT;
+}
+__device__ __forceinline__ double sR(const MechTables* __restrict__ M, int s, double T, double lnT) {
+  const double* a = M->sc[s];
+  return a[0] * lnT + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5];
+}
+
+// Neufeld-Janzen-Aziz collision integrals; x = ln T - ln(eps/k), Ts = T/(eps/k).
+__device__ __forceinline__ double om22(double x, double Ts) {
+  return 1.16145 * exp(-0.14874 * x) + 0.52487 * exp(-0.77320 * Ts) + 2.16178 * exp(-2.43787 * Ts);
+}
+__device__ __forceinline__ double om11(double x, double Ts) {
+  return 1.06036 * exp(-0.15610 * x) + 0.19300 * exp(-0.47635 * Ts) + 1.03587 * exp(-1.52996 * Ts) +
+         1.76474 * exp(-3.89411 * Ts);
+}
+
+__device__ __forceinline__ double laser_axis(const LaserDev& L, const Member& G, int a, int i) {
+  if (!G.act[a]) return 1.0;
+  const double Lp = G.L[a];
+  double r = G.xnode[a][i] - L.xc[a];
+  r -= Lp * rint(r / Lp);
+  double g = 0.0;
+  for (int m = -L.M[a]; m <= L.M[a]; ++m) {
+    const double z = (r - m * Lp) / L.sr;
+    g += exp(-0.5 * z * z);
+  }
+  return g;
+}
+
+// ----------------------------------------------------------- prim -> cons
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_prim_to_cons(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                      int nmem, const double* __restrict__ Yb,
+                                                      const double* __restrict__ Tb, const double* __restrict__ pb,
+                                                      const double* __restrict__ vb, double* __restrict__ Ub) {
+  const int m = find_member(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const double* Y = Yb + NS * G.off;
+  const double* vel = vb + 3 * G.off;
+  double* U = Ub + (NS + 4) * G.off;
+  const double T = Tb[G.off + q], p = pb[G.off + q], iT = 1.0 / T;
+  double iW = 0.0, hm = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double y = Y[s * N + q];
+    iW += y * M->iW[s];
+    hm += y * M->RW[s] * T * hRT(M, s, T, iT);
+  }
+  const double rho = p / (RU * T * iW);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) U[s * N + q] = rho * Y[s * N + q];
+  double ke = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double v = vel[a * N + q];
+    U[(NS + a) * N + q] = rho * v;
+    ke += v * v;
+  }
+  U[(NS + 3) * N + q] = rho * hm - p + 0.5 * rho * ke;
+}
+
+// ------------------------------------------------------------------ point
+// aux rows per cell: 0 p, 1 c, 2 mu, 3 lambda, 4..6 velocity, 7.. D_s.
+// src rows: 0..NS-1 wdot_s, NS q_L.  blkred per block: {sum dV hrr, min dt limit}.
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                               int nmem, CallArgs A, const double* __restrict__ Ub,
+                                               double* __restrict__ Tb, double* __restrict__ auxb,
+                                               double* __restrict__ srcb, double* __restrict__ hrrb,
+                                               double* __restrict__ blkred, double* __restrict__ cellsb,
+                                               unsigned* __restrict__ status, int want_dt) {
+  constexpr int NV = NS + 4, NAUX = 7 + NS;
+  __shared__ double conc[NS][BLK];
+  __shared__ double wred[2][BLK / 64];
+  const int m = find_member(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const int tid = threadIdx.x;
+  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + tid;
+  const bool live = q < G.N;
+  const long long N = G.N;
+  const unsigned flags = A.flags;
+  double hdv = 0.0, lim = INFINITY;
+  if (live) {
+    const double* U = Ub + NV * G.off;
+    double* aux = auxb + NAUX * G.off;
+    double* src = srcb + (NS + 1) * G.off;
+    double r[NS], Y[NS];
+    double rho = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      r[s] = U[s * N + q];
+      rho += r[s];
+      finite = finite && isfinite(r[s]);
+    }
+    const double mx = U[NS * N + q], my = U[(NS + 1) * N + q], mz = U[(NS + 2) * N + q];
+    const double E = U[(NS + 3) * N + q];
+    finite = finite && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(E);
+    unsigned err = 0;
+    if (!finite || !(rho > 0.0)) err = ST_NONFINITE;
+    const double irho = 1.0 / rho;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Y[s] = r[s] * irho;
+    const double u = mx * irho, v = my * irho, w = mz * irho;
+    const double e = E * irho - 0.5 * (u * u + v * v + w * w);
+    // temperature: Newton on e(T) = sum_s Y_s (h_s - R_u T / W_s); converge, then one more step
+    double T = Tb[G.off + q];
+    bool conv = false;
+    if (!err) {
+      for (int it = 0; it < 50; ++it) {
+        const double iT = 1.0 / T;
+        double eT = 0.0, cv = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const double yr = Y[s] * M->RW[s];
+          eT += yr * T * (hRT(M, s, T, iT) - 1.0);
+          cv += yr * (cpR(M, s, T) - 1.0);
+        }
+        const double dT = (eT - e) / cv;
+        T -= dT;
+        if (!isfinite(T) || !(T > 0.0)) break;
+        if (fabs(dT) <= 1e-12 * fabs(T)) {
+          const double iT2 = 1.0 / T;
+          double eT2 = 0.0, cv2 = 0.0;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const double yr = Y[s] * M->RW[s];
+            eT2 += yr * T * (hRT(M, s, T, iT2) - 1.0);
+            cv2 += yr * (cpR(M, s, T) - 1.0);
+          }
+          T -= (eT2 - e) / cv2;
+          conv = true;
+          break;
+        }
+      }
+      if (!conv) err = ST_NEWTON;
+      else if (T < M->Tmin || T > M->Tmax) err = ST_TRANGE;
+    }
+    if (err) {
+      atomicOr(status, err);
+      T = NAN;
+    }
+    Tb[G.off + q] = T;
+    const double iT = 1.0 / T;
+    double iWm = 0.0, cp = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      iWm += Y[s] * M->iW[s];
+      cp += Y[s] * M->RW[s] * cpR(M, s, T);
+    }
+    const double Wm = 1.0 / iWm;
+    const double p = rho * RU * T * iWm;
+    const double c = sqrt(cp / (cp - RU * iWm) * p * irho);
+    double X[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) X[s] = Y[s] * Wm * M->iW[s];
+
+    // ---- transport
+    const double lnT = log(T), sqT = sqrt(T);
+    double mus[NS], lams[NS], smu[NS], ismu[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double Ts = T * M->ieps[s];
+      mus[s] = M->mu_pre[s] * sqT / om22(lnT - M->lneps[s], Ts);
+      lams[s] = mus[s] * (M->RW[s] * cpR(M, s, T) + M->euck[s]);
+      smu[s] = sqrt(mus[s]);
+      ismu[s] = 1.0 / smu[s];
+    }
+    double mu = 0.0, lam = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      double den = 0.0;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const double t1 = 1.0 + smu[i] * ismu[j] * M->wq[i][j];
+        den += X[j] * (t1 * t1 * M->wp[i][j]);
+      }
+      const double id = 1.0 / den;
+      mu += X[i] * mus[i] * id;
+      lam += X[i] * lams[i] * id;
+    }
+    double Dacc[NS], Ds[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Dacc[s] = 0.0;
+    const double T15 = T * sqT;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+#pragma unroll
+      for (int j = i + 1; j < NS; ++j) {
+        const double Ts = T * M->Dieps[i][j];
+        const double iD = p * om11(lnT - M->Dlneps[i][j], Ts) / (M->Dpre[i][j] * T15);
+        Dacc[i] += fmax(X[j], 0.0) * iD;
+        Dacc[j] += fmax(X[i], 0.0) * iD;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (Dacc[s] < 1e-300) {
+        const double Ts = T * M->Dieps[s][s];
+        Ds[s] = M->Dpre[s][s] * T15 / (p * om11(lnT - M->Dlneps[s][s], Ts));
+      } else {
+        Ds[s] = (1.0 - Y[s]) / Dacc[s];
+      }
+    }
+    aux[0 * N + q] = p;
+    aux[1 * N + q] = c;
+    aux[2 * N + q] = mu;
+    aux[3 * N + q] = lam;
+    aux[4 * N + q] = u;
+    aux[5 * N + q] = v;
+    aux[6 * N + q] = w;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) aux[(7 + s) * N + q] = Ds[s];
+
+    // ---- chemistry
+    double om[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) om[s] = 0.0;
+    double hrr = 0.0;
+    if (!(flags & HTR_CHEM_OFF)) {
+      double Gs[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        conc[s][tid] = r[s] * M->iW[s];
+        Gs[s] = hRT(M, s, T, iT) - sR(M, s, T, lnT);
+      }
+      const double lnP = log(PREF / (RU * T));
+      const double* dlnA = A.dlnA ? A.dlnA : G.dlnA;
+      const int nr = M->nr;
+      for (int j = 0; j < nr; ++j) {
+        double lnkf = M->lnA[j] + M->beta[j] * lnT - M->EaR[j] * iT;
+        if (dlnA) lnkf += dlnA[j];
+        double lnKc = M->dnu[j] * lnP;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) lnKc -= M->nunet[j][s] * Gs[s];
+        double rf = exp(lnkf), rb = exp(lnkf - lnKc);
+        for (int e = 0; e < M->nre[j]; ++e) {
+          const double cs = conc[M->ridx[j][e]][tid];
+          for (int k = 0; k < M->rnu[j][e]; ++k) rf *= cs;
+        }
+        for (int e = 0; e < M->npr[j]; ++e) {
+          const double cs = conc[M->pidx[j][e]][tid];
+          for (int k = 0; k < M->pnu[j][e]; ++k) rb *= cs;
+        }
+        const double qj = rf - rb;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) om[s] += M->nunet[j][s] * qj;
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        om[s] *= M->W[s];
+        hrr -= M->RW[s] * T * hRT(M, s, T, iT) * om[s];
+      }
+    }
+    // ---- laser
+    const int i = (int)(q % G.n[0]), jj = (int)((q / G.n[0]) % G.n[1]), k = (int)(q / ((long long)G.n[0] * G.n[1]));
+    const LaserDev& L = A.use_call_laser ? A.laser : G.laser;
+    double qL = 0.0;
+    if (L.on) {
+      const double tk = (A.t_dev ? A.t_dev[m] : A.t) + (A.dt_dev ? A.tcoef * A.dt_dev[m] : 0.0);
+      const double tt = (tk - L.t0) / L.st;
+      qL = L.E * L.norm * laser_axis(L, G, 0, i) * laser_axis(L, G, 1, jj) * laser_axis(L, G, 2, k) *
+           exp(-0.5 * tt * tt);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) src[s * N + q] = om[s];
+    src[NS * N + q] = qL;
+    if (hrrb) hrrb[G.off + q] = hrr;
+    const double xi0 = G.xin[0][i], xi1 = G.xin[1][jj], xi2 = G.xin[2][k];
+    hdv = hrr / (xi0 * xi1 * xi2);
+    if (want_dt) {
+      double sc = 0.0, sd = 0.0;
+      const double uu[3] = {u, v, w}, xx[3] = {xi0, xi1, xi2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (!G.act[a]) continue;
+        sc += (fabs(uu[a]) + c) * xx[a];
+        sd += xx[a] * xx[a];
+      }
+      double nu = fmax(mu * irho, lam / (rho * cp));
+#pragma unroll
+      for (int s = 0; s < NS; ++s) nu = fmax(nu, Ds[s]);
+      if (sc > 0.0) lim = 1.0 / sc;
+      if (!(flags & HTR_VISC_OFF) && sd > 0.0) lim = fmin(lim, 1.0 / (2.0 * sd * nu));
+    }
+    if (cellsb) {
+      double* out = cellsb + (5 + 2 * NS + 3) * G.off;
+      int row = 0;
+      out[(row++) * N + q] = T;
+      out[(row++) * N + q] = p;
+      out[(row++) * N + q] = c;
+      out[(row++) * N + q] = mu;
+      out[(row++) * N + q] = lam;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) out[(row++) * N + q] = Ds[s];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) out[(row++) * N + q] = om[s];
+      out[(row++) * N + q] = hrr;
+      out[(row++) * N + q] = qL;
+    }
+  }
+  if (blkred) {
+    // deterministic block reduction: butterfly within each wavefront, then in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      hdv += __shfl_xor(hdv, o, 64);
+      lim = fmin(lim, __shfl_xor(lim, o, 64));
+    }
+    if ((tid & 63) == 0) {
+      wred[0][tid >> 6] = hdv;
+      wred[1][tid >> 6] = lim;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sh = 0.0, sl = INFINITY;
+      for (int k = 0; k < BLK / 64; ++k) {
+        sh += wred[0][k];
+        sl = fmin(sl, wred[1][k]);
+      }
+      blkred[2 * blockIdx.x] = sh;
+      blkred[2 * blockIdx.x + 1] = sl;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- sensor
+// theta = (div u)^2 / ((div u)^2 + |curl u|^2 + 1e-300) with second-order
+// central differences; flag = theta > theta_c.
+__global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, int nmem,
+                                                const double* __restrict__ auxb, int naux,
+                                                unsigned char* __restrict__ flagb, double theta_c,
+                                                double* __restrict__ theta_out, int nq) {
+  const int m = find_member(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const double* vel = auxb + naux * G.off + 4 * N;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  double g[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm) g[a][mm] = 0.0;
+    if (!G.act[a]) continue;
+    const long long qp = q + (wrapi(c[a] + 1, G.n[a]) - c[a]) * stride[a];
+    const long long qm = q + (wrapi(c[a] - 1, G.n[a]) - c[a]) * stride[a];
+    const double xi = G.xin[a][c[a]];
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm) g[a][mm] = xi * (vel[mm * N + qp] - vel[mm * N + qm]) / 2.0;
+  }
+  const double div = g[0][0] + g[1][1] + g[2][2];
+  const double wx = g[1][2] - g[2][1], wy = g[2][0] - g[0][2], wz = g[0][1] - g[1][0];
+  const double d2 = div * div;
+  const double th = d2 / (d2 + wx * wx + wy * wy + wz * wz + 1e-300);
+  flagb[G.off + q] = th > theta_c ? 1 : 0;
+  if (theta_out) theta_out[(nq - 1) * N + nq * G.off + q] = th;
+}
+
+// ------------------------------------------------------------- reductions
+// One block per member: fixed-order sums of that member's block partials.
+__global__ __launch_bounds__(BLK) void k_finalize(const Member* __restrict__ mem, const double* __restrict__ blkred,
+                                                  double cfl, double* __restrict__ dt_dev, double* __restrict__ J_dev,
+                                                  const double* __restrict__ dt_in, double jcoef, int want_dt) {
+  __shared__ double sh[BLK], sl[BLK];
+  const Member& G = mem[blockIdx.x];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = INFINITY;
+  for (int k = tid; k < G.nblocks; k += BLK) {
+    a += blkred[2 * (G.block_begin + k)];
+    b = fmin(b, blkred[2 * (G.block_begin + k) + 1]);
+  }
+  sh[tid] = a;
+  sl[tid] = b;
+  __syncthreads();
+  for (int o = BLK / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      sh[tid] += sh[tid + o];
+      sl[tid] = fmin(sl[tid], sl[tid + o]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double dt = 0.0;
+    if (want_dt) {
+      dt = cfl * sl[0];
+      dt_dev[blockIdx.x] = dt;
+    } else if (dt_in) {
+      dt = dt_in[blockIdx.x];
+    }
+    if (J_dev) J_dev[blockIdx.x] += jcoef * dt * sh[0];
+  }
+}
+
+__global__ void k_advance_time(int nmem, double* __restrict__ t_dev, const double* __restrict__ dt_dev) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < nmem) t_dev[m] += dt_dev[m];
+}
+
+// ---------------------------------------------------------------- launchers
+template <int NS>
+static hipError_t prim_to_cons_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const double* Y,
+                                 const double* T, const double* p, const double* vel, double* U, hipStream_t s) {
+  hipLaunchKernelGGL(k_prim_to_cons<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, nmem, Y, T, p, vel, U);
+  return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t point_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                          const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
+                          double* cells, unsigned* status, int want_dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_point<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, T, aux, src, hrr, blkred,
+                     cells, status, want_dt);
+  return hipGetLastError();
+}
+
+#define HTR_NS_SWITCH(ns, CALL)                                                        \
+  switch (ns) {                                                                        \
+    case 1: return CALL(1); case 2: return CALL(2); case 3: return CALL(3);            \
+    case 4: return CALL(4); case 5: return CALL(5); case 6: return CALL(6);            \
+    case 7: return CALL(7); case 8: return CALL(8); case 9: return CALL(9);            \
+    case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12);      \
+    default: return hipErrorInvalidValue;                                              \
+  }
+
+hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
+                               const double* Y, const double* T, const double* p, const double* vel, double* U,
+                               hipStream_t s) {
+#define C_(NS) prim_to_cons_t<NS>(M, mem, nmem, nblocks, Y, T, p, vel, U, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                        const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
+                        double* cells, unsigned* status, int want_dt, hipStream_t s) {
+#define C_(NS) point_t<NS>(M, mem, nmem, nblocks, a, U, T, aux, src, hrr, blkred, cells, status, want_dt, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
+                         double theta_c, double* theta_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, nmem, aux, 7 + ns, flag, theta_c, theta_out,
+                     5 + 2 * ns + 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_time, dim3((nmem + 63) / 64), dim3(64), 0, s, nmem, t_dev, dt_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
+                           double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nmem), dim3(BLK), 0, s, mem, blkred, cfl, dt_dev, J_dev, dt_in, jcoef, want_dt);
+  return hipGetLastError();
+}
+
+}  // namespace htr

@@ -1,0 +1,188 @@
+"""Python binding of the C interface (include/htr.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the computation runs in the HIP kernels
+of libhtr.so.  Functions carry the names of the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HTRError, check, htr_grid_desc, htr_laser, htr_mech_desc, htr_scheme  # noqa: F401
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if t.dtype not in (torch.float64, torch.uint8):
+        raise ValueError(f"float64 tensor required, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def make_laser(laser) -> htr_laser | None:
+    """htr_laser from an object with E, center, sigma_r, t0, sigma_t, on (or None)."""
+    if laser is None:
+        return None
+    L = htr_laser()
+    L.E = float(laser.E)
+    for a in range(3):
+        L.center[a] = float(laser.center[a])
+    L.sigma_r = float(laser.sigma_r)
+    L.t0 = float(laser.t0)
+    L.sigma_t = float(laser.sigma_t)
+    L.on = 1 if laser.on else 0
+    return L
+
+
+class Context:
+    """Owns an htr_ctx for one mechanism, grid and scheme."""
+
+    def __init__(self, mech, grid, *, cfl=0.5, theta_c=0.1, psi_c=0.05, teno_CT=1e-5, flags=0):
+        lib = _lib.load()
+        self._keep = []
+        md = htr_mech_desc()
+        md.ns, md.nr = int(mech.ns), int(mech.nr)
+
+        def dp(a):
+            a = _f64(a)
+            if a.size == 0:
+                a = np.zeros(1)
+            self._keep.append(a)
+            return a.ctypes.data_as(_lib._dp)
+
+        def ip(a):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.int32)).reshape(-1)
+            if a.size == 0:
+                a = np.zeros(1, np.int32)
+            self._keep.append(a)
+            return a.ctypes.data_as(_lib._ip)
+        md.W, md.nasa7 = dp(mech.W), dp(np.asarray(mech.nasa7).reshape(-1))
+        md.lj_sigma, md.lj_epsk = dp(mech.lj_sigma), dp(mech.lj_epsk)
+        md.lnA, md.beta, md.Ea = dp(mech.lnA), dp(mech.beta), dp(mech.Ea)
+        md.nu_f, md.nu_r = ip(mech.nu_f), ip(mech.nu_r)
+        md.Tmin, md.Tmax = float(mech.Tmin), float(mech.Tmax)
+        gd = htr_grid_desc()
+        for a in range(3):
+            gd.n[a] = int(grid.n[a])
+            gd.xnode[a] = dp(grid.xnode[a])
+            gd.xi_node[a] = dp(grid.xin[a])
+            gd.xi_face[a] = dp(grid.xif[a])
+            gd.L[a] = float(grid.L[a])
+        sc = htr_scheme(cfl=cfl, theta_c=theta_c, psi_c=psi_c, teno_CT=teno_CT, flags=flags)
+        h = C.c_void_p()
+        check(lib.htr_create(C.byref(md), C.byref(gd), C.byref(sc), C.byref(h)))
+        self.h = h
+        self.lib = lib
+        self.ns, self.nr = md.ns, md.nr
+        self.nv = self.ns + 4
+        self.N = int(lib.htr_num_cells(h))
+        self.n = tuple(int(v) for v in grid.n)
+        self.flags = flags
+        self._keep = []
+
+    @classmethod
+    def from_case(cls, case, flags=None):
+        return cls(case.mech, case.grid, cfl=case.cfl, theta_c=case.theta_c, psi_c=case.psi_c,
+                   teno_CT=case.teno_CT, flags=case.flags if flags is None else flags)
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(self.lib.htr_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_flags(self, flags):
+        check(self.lib.htr_set_flags(self.h, int(flags)))
+        self.flags = flags
+
+    def work_bytes(self):
+        return int(self.lib.htr_work_bytes(self.h))
+
+    def new_work(self, device="cuda"):
+        return torch.empty(self.work_bytes() // 8, dtype=torch.float64, device=device)
+
+
+# ------------------------------------------------------------ C-name binding
+def htr_prim_to_cons(ctx, Y, T, p, vel, U, stream=None):
+    check(ctx.lib.htr_prim_to_cons(ctx.h, _ptr(Y), _ptr(T), _ptr(p), _ptr(vel), _ptr(U), _stream(stream)))
+
+
+def htr_rhs(ctx, U, T_io, t, laser, dUdt, hrr=None, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rhs(ctx.h, _ptr(U), _ptr(T_io), float(t), C.byref(L) if L else None, _ptr(dUdt),
+                          _ptr(hrr), _stream(stream)))
+
+
+def htr_cells(ctx, U, T_io, t, laser, out, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_cells(ctx.h, _ptr(U), _ptr(T_io), float(t), C.byref(L) if L else None, _ptr(out),
+                            _stream(stream)))
+
+
+def htr_stable_dt(ctx, U, T_io, dt_dev, stream=None):
+    check(ctx.lib.htr_stable_dt(ctx.h, _ptr(U), _ptr(T_io), _ptr(dt_dev), _stream(stream)))
+
+
+def htr_work_bytes(ctx):
+    return int(ctx.lib.htr_work_bytes(ctx.h))
+
+
+def htr_rk3_step(ctx, U, T_io, t_dev, dt_dev, compute_dt, laser, dlnA_dev, work, J_dev=None, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rk3_step(ctx.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dt_dev), int(compute_dt),
+                               C.byref(L) if L else None, _ptr(dlnA_dev), _ptr(work), _ptr(J_dev), _stream(stream)))
+
+
+def htr_timing(ctx, enable):
+    check(ctx.lib.htr_timing(ctx.h, int(enable)))
+
+
+KERNEL_CLASSES = ("point", "sensor", "sweep", "reduce")
+
+
+def htr_timing_read(ctx):
+    """{class: (total ms, launches)} since htr_timing(ctx, 1)."""
+    ms = (C.c_double * 4)()
+    n = (C.c_int64 * 4)()
+    check(ctx.lib.htr_timing_read(ctx.h, ms, n))
+    return {KERNEL_CLASSES[k]: (ms[k], n[k]) for k in range(4)}
+
+
+def htr_check(ctx, stream=None):
+    check(ctx.lib.htr_check(ctx.h, _stream(stream)))
+
+
+# ------------------------------------------------------------ conveniences
+def to_dev(a, device="cuda"):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def cons_from_case(ctx, case, device="cuda"):
+    """U on the device from the case's primitive fields (GPU conversion)."""
+    U = torch.empty((ctx.nv, ctx.N), dtype=torch.float64, device=device)
+    htr_prim_to_cons(ctx, to_dev(case.Y, device), to_dev(case.T, device), to_dev(case.p, device),
+                     to_dev(case.vel, device), U)
+    return U
