@@ -194,6 +194,51 @@ htr_status htr_rk3_step(htr_ctx* ctx, double* U, double* T_io, double* t_dev, do
 htr_status htr_timing(htr_ctx* ctx, int enable);
 htr_status htr_timing_read(htr_ctx* ctx, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent grids (members) sharing the context's
+ * mechanism and scheme, advanced together (the paper's ensemble workflow,
+ * Sec. 2 and Sec. 6: samples with perturbed laser energy, position and
+ * rates).  Member m owns cells [off_m, off_m + N_m) of packed arrays: a
+ * [rows][N] field of the member starts at base + rows * off_m.  Each member
+ * has its own uniform periodic grid, laser kernel, ln A offsets, time, step
+ * and heat-release accumulator.  Every kernel of a batched call is ONE launch
+ * covering the tiles of all members.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n[3];          /* member grid                                        */
+  double dx[3];          /* uniform spacing (for an inactive axis: its width)  */
+  htr_laser laser;       /* member's deposition kernel                         */
+  const double* dlnA;    /* HOST [nr] ln A offsets of the member, nullable     */
+} htr_member_desc;
+
+/* Create an ensemble of nmem members on the context's mechanism and scheme.
+ * Descriptors are HOST memory, copied.  Errors: HTR_EINVAL (nmem < 1, bad
+ * member), HTR_ENOMEM, HTR_EDEVICE. */
+htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* members, htr_batch** out);
+htr_status htr_batch_destroy(htr_batch* b);
+/* Total packed cells; if offsets (HOST, nmem + 1 entries) is non-NULL it
+ * receives the member cell offsets (offsets[nmem] = total). */
+int64_t htr_batch_cells(const htr_batch* b, int64_t* offsets);
+/* Packed primitive fields Y[ns], T, p, vel[3] -> packed U (as htr_prim_to_cons). */
+htr_status htr_batch_prim_to_cons(htr_batch* b, const double* Y, const double* T, const double* p,
+                                  const double* vel, double* U, void* stream);
+/* One right-hand side of every member at its own time t_dev[m] (device
+ * [nmem]); packed U in, packed dUdt out, packed T_io in/out, hrr nullable. */
+htr_status htr_rhs_batched(htr_batch* b, const double* U, double* T_io, const double* t_dev, double* dUdt,
+                           double* hrr, void* stream);
+size_t htr_batch_work_bytes(const htr_batch* b);
+/* nsteps SSP-RK3 steps of every member (each with its own dt; with
+ * compute_dt each member's dt is its own stable step, as htr_rk3_step).
+ * t_dev, dt_dev, J_dev (nullable) are device [nmem].  With use_graph != 0
+ * the nsteps steps are captured once into a HIP graph (re-captured when any
+ * pointer argument, nsteps or compute_dt changes) and replayed with one
+ * graph launch per call. */
+htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* t_dev, double* dt_dev,
+                                 int compute_dt, int nsteps, double* work, double* J_dev, int use_graph,
+                                 void* stream);
+/* As htr_check, for the ensemble's status word. */
+htr_status htr_batch_check(htr_batch* b, void* stream);
+
 /* Synchronises `stream`, returns the first device-side error latched since
  * the last htr_check (and clears it), or HTR_EDEVICE for a HIP error. */
 htr_status htr_check(htr_ctx* ctx, void* stream);

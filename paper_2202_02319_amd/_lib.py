@@ -34,6 +34,10 @@ class htr_laser(C.Structure):
                 ("sigma_t", C.c_double), ("on", C.c_int32)]
 
 
+class htr_member_desc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dx", C.c_double * 3), ("laser", htr_laser), ("dlnA", _dp)]
+
+
 class htr_scheme(C.Structure):
     _fields_ = [("cfl", C.c_double), ("theta_c", C.c_double), ("psi_c", C.c_double), ("teno_CT", C.c_double),
                 ("flags", C.c_uint32)]
@@ -73,6 +77,14 @@ def load():
         "htr_timing": (st, [vp, C.c_int]),
         "htr_timing_read": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "htr_check": (st, [vp, vp]),
+        "htr_batch_create": (st, [vp, C.c_int32, C.POINTER(htr_member_desc), C.POINTER(vp)]),
+        "htr_batch_destroy": (st, [vp]),
+        "htr_batch_cells": (C.c_int64, [vp, C.POINTER(C.c_int64)]),
+        "htr_batch_prim_to_cons": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "htr_rhs_batched": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "htr_batch_work_bytes": (C.c_size_t, [vp]),
+        "htr_rk3_steps_batched": (st, [vp, vp, vp, vp, vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
+        "htr_batch_check": (st, [vp, vp]),
         "htr_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -18,8 +18,8 @@ using namespace htr;
 
 static thread_local std::string g_last_error;
 
-static htr_status fail(htr_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static htr_status fail(htr_status st, const char* fmt, ...) {
+namespace htr {
+htr_status fail(htr_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -28,12 +28,7 @@ static htr_status fail(htr_status st, const char* fmt, ...) {
   g_last_error = buf;
   return st;
 }
-
-#define HIP_OK(expr)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess) return fail(HTR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace htr
 
 namespace htr {
 
@@ -160,22 +155,6 @@ htr_status build_tables(const htr_mech_desc* m, MechTables* T) {
 }
 
 }  // namespace htr
-
-struct htr_ctx {
-  int device = 0;
-  int ns = 0, nr = 0;
-  htr_scheme scheme{};
-  MechTables* dM = nullptr;      // device tables
-  Member host_mem{};             // single member (host copy)
-  Member* dmem = nullptr;        // device member table (one entry)
-  double* dgrid = nullptr;       // device metric/coordinate arrays
-  int n[3] = {1, 1, 1};
-  double L[3] = {0, 0, 0};
-  long long N = 0;
-  int nblocks = 0;
-  Workspace ws;
-  Timer timer;
-};
 
 namespace htr {
 

@@ -9,6 +9,15 @@
 
 namespace htr {
 
+// Sets the calling thread's last-error message and returns st.
+htr_status fail(htr_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_OK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return ::htr::fail(HTR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
 // Scratch owned by a context or an ensemble: per-cell derived fields,
 // sources, sensor flags, block partials, status word.
 struct Workspace {
@@ -70,3 +79,19 @@ htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t
                hipStream_t s);
 
 }  // namespace htr
+
+struct htr_ctx {
+  int device = 0;
+  int ns = 0, nr = 0;
+  htr_scheme scheme{};
+  htr::MechTables* dM = nullptr;   // device tables
+  htr::Member host_mem{};          // single member (host copy)
+  htr::Member* dmem = nullptr;     // device member table (one entry)
+  double* dgrid = nullptr;         // device metric/coordinate arrays
+  int n[3] = {1, 1, 1};
+  double L[3] = {0, 0, 0};
+  long long N = 0;
+  int nblocks = 0;
+  htr::Workspace ws;
+  htr::Timer timer;
+};

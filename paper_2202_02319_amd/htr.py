@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import HTRError, check, htr_grid_desc, htr_laser, htr_mech_desc, htr_scheme  # noqa: F401
+from ._lib import HTRError, check, htr_grid_desc, htr_laser, htr_mech_desc, htr_member_desc, htr_scheme  # noqa: F401,E501
 
 
 def _ptr(t):
@@ -186,3 +186,93 @@ def cons_from_case(ctx, case, device="cuda"):
     htr_prim_to_cons(ctx, to_dev(case.Y, device), to_dev(case.T, device), to_dev(case.p, device),
                      to_dev(case.vel, device), U)
     return U
+
+
+# ------------------------------------------------------------------ ensembles
+class Batch:
+    """Owns an htr_batch: members (grids with uniform spacing, lasers, ln A
+    offsets) on a context's mechanism and scheme."""
+
+    def __init__(self, ctx, grids, lasers, dlnA=None):
+        lib = ctx.lib
+        nmem = len(grids)
+        descs = (htr_member_desc * nmem)()
+        self._keep = []
+        for m in range(nmem):
+            g = grids[m]
+            d = descs[m]
+            for a in range(3):
+                d.n[a] = int(g.n[a])
+                d.dx[a] = float(1.0 / g.xin[a][0])
+            L = make_laser(lasers[m]) if lasers[m] is not None else htr_laser()
+            d.laser = L
+            if dlnA is not None:
+                arr = np.ascontiguousarray(np.asarray(dlnA[m], dtype=np.float64))
+                self._keep.append(arr)
+                d.dlnA = arr.ctypes.data_as(_lib._dp)
+        h = C.c_void_p()
+        check(lib.htr_batch_create(ctx.h, nmem, descs, C.byref(h)))
+        self.h, self.lib, self.ctx = h, lib, ctx
+        self.nmem = nmem
+        offs = (C.c_int64 * (nmem + 1))()
+        self.N = int(lib.htr_batch_cells(h, offs))
+        self.offsets = [int(offs[m]) for m in range(nmem + 1)]
+        self._keep = []
+
+    @classmethod
+    def from_cases(cls, ctx, cases, dlnA=None):
+        return cls(ctx, [c.grid for c in cases], [c.laser if c.laser.on else None for c in cases], dlnA)
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(self.lib.htr_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_work(self, device="cuda"):
+        return torch.empty(int(self.lib.htr_batch_work_bytes(self.h)) // 8, dtype=torch.float64, device=device)
+
+    def pack(self, arrays, rows):
+        """Packs per-member host arrays [rows][N_m] (or [N_m]) member-major."""
+        parts = [np.asarray(a, dtype=np.float64).reshape(rows, -1) for a in arrays]
+        return np.concatenate([p.ravel() for p in parts])
+
+    def unpack(self, flat, rows, m):
+        o0, o1 = self.offsets[m], self.offsets[m + 1]
+        return np.asarray(flat)[rows * o0: rows * o1].reshape(rows, o1 - o0)
+
+
+def htr_batch_prim_to_cons(b, Y, T, p, vel, U, stream=None):
+    check(b.lib.htr_batch_prim_to_cons(b.h, _ptr(Y), _ptr(T), _ptr(p), _ptr(vel), _ptr(U), _stream(stream)))
+
+
+def htr_rhs_batched(b, U, T_io, t_dev, dUdt, hrr=None, stream=None):
+    check(b.lib.htr_rhs_batched(b.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dUdt), _ptr(hrr), _stream(stream)))
+
+
+def htr_rk3_steps_batched(b, U, T_io, t_dev, dt_dev, compute_dt, nsteps, work, J_dev=None, use_graph=False,
+                          stream=None):
+    check(b.lib.htr_rk3_steps_batched(b.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dt_dev), int(compute_dt),
+                                      int(nsteps), _ptr(work), _ptr(J_dev), int(bool(use_graph)),
+                                      _stream(stream)))
+
+
+def htr_batch_check(b, stream=None):
+    check(b.lib.htr_batch_check(b.h, _stream(stream)))
+
+
+def batch_state_from_cases(b, cases, device="cuda"):
+    """Packed U (GPU conversion) and T for a list of member cases."""
+    ns = b.ctx.ns
+    Y = to_dev(b.pack([c.Y for c in cases], ns), device)
+    T = to_dev(b.pack([c.T for c in cases], 1), device)
+    p = to_dev(b.pack([c.p for c in cases], 1), device)
+    vel = to_dev(b.pack([c.vel for c in cases], 3), device)
+    U = torch.empty(b.N * (ns + 4), dtype=torch.float64, device=device)
+    htr_batch_prim_to_cons(b, Y, T, p, vel, U)
+    return U, T
