@@ -92,6 +92,62 @@ def cpu_baseline(case, seconds_target=15.0):
                       f"slab of the workload, {el:.2f} s"}
 
 
+def ensemble_measure(steps, warm=1):
+    """The 64-member ensemble (N^3 members, N uniform on {32, 40, ..., 96},
+    perturbed deposition energy, kernel centre and ln A): `steps` RK3 steps
+    of all members as one captured HIP-graph launch (one launch per kernel
+    over all members' tiles), against the same steps driven member by member
+    (one htr_rk3_step per member and step, one stream)."""
+    import torch
+    import synth
+    from paper_2202_02319_amd import htr
+    e = synth.ensemble_c4()
+    ctx = htr.Context(e.mech, e.members[0].grid)
+    b = htr.Batch.from_cases(ctx, e.members, e.dlnA)
+    U, T = htr.batch_state_from_cases(b, e.members)
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")  # noqa: E731
+    t, dt, J = z(b.nmem), z(b.nmem), z(b.nmem)
+    work = b.new_work()
+    stream = torch.cuda.current_stream()
+    htr.htr_rk3_steps_batched(b, U, T, t, dt, 1, steps, work, J, use_graph=True)   # capture + warm-up
+    torch.cuda.synchronize()
+    htr.htr_batch_check(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    htr.htr_rk3_steps_batched(b, U, T, t, dt, 1, steps, work, J, use_graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    htr.htr_batch_check(b)
+    t_b = e0.elapsed_time(e1) / 1e3
+    del U, T, work
+    # member by member
+    mems = []
+    for m, c in enumerate(e.members):
+        g = htr.Context(e.mech, c.grid)
+        mems.append((g, htr.cons_from_case(g, c), htr.to_dev(c.T), z(1), z(1), z(1), g.new_work(),
+                     htr.to_dev(e.dlnA[m]), c.laser))
+
+    def per_member(nst):
+        for _ in range(nst):
+            for (g, Um, Tm, tm, dtm, Jm, wm, dl, las) in mems:
+                htr.htr_rk3_step(g, Um, Tm, tm, dtm, 1, las, dl, wm, Jm)
+    per_member(warm)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    per_member(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    for g, *_ in mems:
+        htr.htr_check(g)
+    t_m = e0.elapsed_time(e1) / 1e3
+    cs = b.N * 3 * steps
+    return {"workload": f"64-member mixing-layer ensemble, N^3 members with N in {{32,...,96}}, {b.N} cells, "
+                        f"{steps} RK3 steps", "cells": b.N, "steps": steps,
+            "batched_value": cs / t_b, "per_member_value": cs / t_m, "unit": "cell-stage updates/s",
+            "batched_over_per_member": t_m / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
+            "per_member_ms_per_step": 1e3 * t_m / steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +156,7 @@ def main():
     ap.add_argument("--workload", choices=["tgv128", "mixing256"], default="tgv128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (ensemble members or grid blocks "
@@ -187,6 +244,10 @@ def main():
                    "cells": N, "species": ns, "reactions": nr, "stages_per_step": 3},
         "roofline": roof,
     }
+    if args.ens_steps > 0:
+        del U, T, work
+        torch.cuda.empty_cache()
+        out["ensemble"] = ensemble_measure(args.ens_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
