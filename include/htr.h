@@ -195,6 +195,42 @@ htr_status htr_timing(htr_ctx* ctx, int enable);
 htr_status htr_timing_read(htr_ctx* ctx, double* ms, int64_t* launches);
 
 /* ------------------------------------------------------------------------
+ * Discrete adjoint (reverse mode), for the time-integrated heat release
+ * J = sum_steps dt sum_k b_k sum_cells dV HRR(U^(k), t_k) and the parameters
+ * theta = (E, centre x, centre y, centre z, ln A_1 .. ln A_nr) of the laser
+ * kernel (Sec. 6.3.1) and of the Arrhenius rates (Sec. 5.1).  The paper
+ * obtains sensitivities from ensembles of forward runs (Sec. 2); this is the
+ * reverse-mode alternative.  Discrete switches (hybrid sensor, TENO
+ * cut-offs, argmax of the Lax-Friedrichs speed, Newton iteration count) are
+ * frozen: the derivative is that of the scheme with those switches fixed,
+ * which is the exact derivative wherever no switch flips.  The Newton
+ * temperature is differentiated through its implicit definition.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of caller-owned scratch the adjoint calls need. */
+size_t htr_adjoint_work_bytes(const htr_ctx* ctx);
+
+/* Vector-Jacobian product of one right-hand side and of its heat release
+ * H = sum_cells dV HRR, at state U and time t:
+ *   Ubar_acc[nv][N] += s (dL/dU)^T lam + h dH/dU
+ *   pbar_acc[4+nr]  += s (dL/dtheta)^T lam + h dH/dtheta
+ * lam [nv][N] is a cotangent of dU/dt.  T_io is the Newton guess cache
+ * (updated).  dlnA_dev (nullable) are the ln A offsets the forward used.
+ * All arrays are device memory; adj_work >= htr_adjoint_work_bytes. */
+htr_status htr_rhs_adjoint(htr_ctx* ctx, const double* U, double* T_io, double t, const htr_laser* laser,
+                           const double* dlnA_dev, const double* lam, double s, double h, double* Ubar_acc,
+                           double* pbar_acc, double* adj_work, void* stream);
+
+/* Adjoint of one htr_rk3_step taken with the fixed step dt from U^n at time
+ * t (and contributing Jbar * its J increment).  Un is U^n; stages is the work
+ * buffer as that htr_rk3_step left it (U1 then U2).  Ubar [nv][N] holds the
+ * cotangent of U^{n+1} on entry and that of U^n on return; pbar_acc[4+nr]
+ * accumulates the parameter cotangent. */
+htr_status htr_rk3_step_adjoint(htr_ctx* ctx, const double* Un, const double* stages, double* T_io, double t,
+                                double dt, const htr_laser* laser, const double* dlnA_dev, double Jbar,
+                                double* Ubar, double* pbar_acc, double* adj_work, void* stream);
+
+/* ------------------------------------------------------------------------
  * Ensembles: many independent grids (members) sharing the context's
  * mechanism and scheme, advanced together (the paper's ensemble workflow,
  * Sec. 2 and Sec. 6: samples with perturbed laser energy, position and

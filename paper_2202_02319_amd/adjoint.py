@@ -1,0 +1,98 @@
+"""Time-integrated heat release and its gradient through the discrete
+adjoint, behind a torch.autograd.Function with step checkpointing.
+
+J(theta) = sum_steps dt sum_k b_k sum_cells dV HRR(U^(k), t_k) for a fixed
+number of SSP-RK3 steps with a frozen step dt, theta = (E, centre x, y, z,
+ln A offsets of every reaction).  The forward pass keeps the state every
+`checkpoint_every` steps; the backward pass re-runs each segment keeping its
+stage states and walks it in reverse with htr_rk3_step_adjoint.  All
+arithmetic runs in the HIP library; torch holds the buffers.
+"""
+from __future__ import annotations
+
+import copy
+
+import torch
+
+from . import htr
+
+
+class HeatReleaseProblem:
+    """A fixed problem: context, initial state, frozen dt, step count."""
+
+    def __init__(self, ctx, U0, T0, laser, dt, nsteps, checkpoint_every=10, t0=0.0):
+        self.ctx, self.U0, self.T0 = ctx, U0.contiguous(), T0.contiguous()
+        self.laser = copy.copy(laser)
+        self.dt, self.nsteps, self.K, self.t0 = float(dt), int(nsteps), int(checkpoint_every), float(t0)
+        self.work = ctx.new_work()
+        self.adj_work = htr.new_adjoint_work(ctx)
+        self.nth = 4 + ctx.nr
+
+    def _laser_for(self, theta):
+        L = copy.copy(self.laser)
+        th = theta.detach().cpu().tolist()
+        L.E = th[0]
+        L.center = (th[1], th[2], th[3])
+        return L
+
+    def _step(self, U, T, t, L, dlnA, J):
+        t_dev = torch.full((1,), t, dtype=torch.float64, device=U.device)
+        dt_dev = torch.full((1,), self.dt, dtype=torch.float64, device=U.device)
+        htr.htr_rk3_step(self.ctx, U, T, t_dev, dt_dev, 0, L, dlnA, self.work, J)
+
+    def forward(self, theta):
+        """J and the checkpoints [(step, U, T)]."""
+        L = self._laser_for(theta)
+        dlnA = theta[4:].detach().contiguous()
+        U, T = self.U0.clone(), self.T0.clone()
+        J = torch.zeros(1, dtype=torch.float64, device=U.device)
+        ckpts = []
+        for n in range(self.nsteps):
+            if n % self.K == 0:
+                ckpts.append((n, U.clone(), T.clone()))
+            self._step(U, T, self.t0 + n * self.dt, L, dlnA, J)
+        htr.htr_check(self.ctx)
+        return J, ckpts
+
+    def backward(self, theta, ckpts, Jbar=1.0):
+        """(dJ/dtheta, dJ/dU0) by the discrete adjoint."""
+        L = self._laser_for(theta)
+        dlnA = theta[4:].detach().contiguous()
+        Ubar = torch.zeros_like(self.U0)
+        pbar = torch.zeros(self.nth, dtype=torch.float64, device=self.U0.device)
+        J = torch.zeros(1, dtype=torch.float64, device=self.U0.device)
+        for (n0, Uc, Tc) in reversed(ckpts):
+            n1 = min(n0 + self.K, self.nsteps)
+            U, T = Uc.clone(), Tc.clone()
+            states, stages, temps = [], [], []
+            for n in range(n0, n1):
+                states.append(U.clone())
+                temps.append(T.clone())
+                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J)
+                stages.append(self.work.clone())
+            for i in reversed(range(n1 - n0)):
+                n = n0 + i
+                Tg = temps[i].clone()
+                htr.htr_rk3_step_adjoint(self.ctx, states[i], stages[i], Tg, self.t0 + n * self.dt, self.dt, L, dlnA,
+                                         Jbar, Ubar, pbar, self.adj_work)
+        htr.htr_check(self.ctx)
+        return pbar, Ubar
+
+
+class HeatReleaseObjective(torch.autograd.Function):
+    """J = HeatReleaseObjective.apply(theta, problem); J.backward() fills
+    theta.grad with dJ/dtheta from the discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, theta, problem):
+        J, ckpts = problem.forward(theta)
+        ctx.problem = problem
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(theta)
+        return J.reshape(())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (theta,) = ctx.saved_tensors
+        pbar, _ = ctx.problem.backward(theta, ctx.ckpts, Jbar=float(gJ))
+        return pbar.to(theta.dtype), None

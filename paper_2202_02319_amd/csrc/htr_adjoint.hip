@@ -1,0 +1,868 @@
+// Discrete adjoint of one right-hand side evaluation and of its heat release.
+//
+// For a cotangent lam of dU/dt (scaled by s) and a seed h of the heat release
+// H = sum_cells dV HRR, these kernels add  s (dL/dU)^T lam + h dH/dU  to an
+// accumulator and s (dL/dtheta)^T lam + h dH/dtheta to the parameter
+// cotangent, theta = (E, centre x, y, z, ln A_1..nr).  The discrete switches
+// (hybrid sensor, TENO cut-offs, the argmax of the Lax-Friedrichs speed, the
+// Newton iteration count) are frozen: they are re-evaluated from the same
+// inputs with the same arithmetic as the forward sweep, and the derivative
+// is that of the scheme with those switches fixed.  The Newton temperature is
+// differentiated through its implicit definition e(T, Y) = e.
+//
+// Two kernels per evaluation, after a forward per-cell pass on the state:
+//   k_adj_sweep  one thread per node: gathers from every face whose stencil
+//                contains the node (six convective faces per direction; two
+//                diffusive faces; four per tangential axis through the
+//                cross-derivatives) the cotangents of the node's conserved
+//                variables (direct) and of its per-cell fields
+//                (T, p, c, mu, lambda, u, D_s).  No atomics: deterministic.
+//   k_adj_point  one thread per cell: reverse of the per-cell physics
+//                (heat release, chemistry, Bird and Wilke transport, EOS,
+//                implicit Newton T), plus the laser's parameter derivatives;
+//                block partials of the parameter cotangent.
+
+#include <math.h>
+
+#include "htr_dev.h"
+#include "htr_flux.h"
+
+namespace htr {
+
+// rows of the per-cell field cotangent array
+constexpr int PB_T = 0, PB_P = 1, PB_C = 2, PB_MU = 3, PB_LAM = 4, PB_U = 5, PB_D = 8;
+
+__device__ __forceinline__ double cpRa(const MechTables* __restrict__ M, int s, double T) {
+  const double* a = M->cp[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+}
+__device__ __forceinline__ double dcpRa(const MechTables* __restrict__ M, int s, double T) {
+  const double* a = M->cp[s];
+  return a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
+}
+__device__ __forceinline__ double hRTa(const MechTables* __restrict__ M, int s, double T, double iT) {
+  const double* a = M->hc[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5] * iT;
+}
+__device__ __forceinline__ double sRa(const MechTables* __restrict__ M, int s, double T, double lnT) {
+  const double* a = M->sc[s];
+  return a[0] * lnT + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5];
+}
+// collision integrals and their temperature derivatives (x = ln T - ln eps, Ts = T/eps)
+__device__ __forceinline__ double om22a(double x, double Ts, double iT, double ieps, double* dT) {
+  const double e0 = 1.16145 * exp(-0.14874 * x), e1 = 0.52487 * exp(-0.77320 * Ts), e2 = 2.16178 * exp(-2.43787 * Ts);
+  *dT = -0.14874 * e0 * iT - (0.77320 * e1 + 2.43787 * e2) * ieps;
+  return e0 + e1 + e2;
+}
+__device__ __forceinline__ double om11a(double x, double Ts, double iT, double ieps, double* dT) {
+  const double e0 = 1.06036 * exp(-0.15610 * x), e1 = 0.19300 * exp(-0.47635 * Ts);
+  const double e2 = 1.03587 * exp(-1.52996 * Ts), e3 = 1.76474 * exp(-3.89411 * Ts);
+  *dT = -0.15610 * e0 * iT - (0.47635 * e1 + 1.52996 * e2 + 3.89411 * e3) * ieps;
+  return e0 + e1 + e2 + e3;
+}
+
+// ------------------------------------------------------------ convective
+template <int NS>
+__device__ __forceinline__ void adj_conv(const Member& G, int d, const int c[3], long long q, long long N,
+                                         const double* __restrict__ U, const double* __restrict__ aux,
+                                         const unsigned char* __restrict__ flag, const double* __restrict__ lam,
+                                         double s, unsigned flags, double psi_c, double CT, double* ubar,
+                                         double* pb) {
+  constexpr int NV = NS + 4;
+  const int n = G.n[d];
+  const long long stride = d == 0 ? 1 : (d == 1 ? (long long)G.n[0] : (long long)G.n[0] * G.n[1]);
+  // window of 11 nodes: relative offsets -5..5
+  long long qo[11];
+  double ud[11], pp[11], cc[11];
+  int fl = 0;
+#pragma unroll
+  for (int o = 0; o < 11; ++o) {
+    qo[o] = q + (long long)(wrapi(c[d] + o - 5, n) - c[d]) * stride;
+    ud[o] = aux[(4 + d) * N + qo[o]];
+    pp[o] = aux[qo[o]];
+    cc[o] = aux[N + qo[o]];
+    fl |= (int)flag[qo[o]] << o;
+  }
+  double xi7[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) xi7[o] = G.xin[d][wrapi(c[d] + o - 3, n)];
+  // faces k = 0..5: left node at offset k-3, stencil offsets k-5..k (window k..k+5)
+  bool te[6], use[6];
+  double al[6];
+  int am[6];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    // a periodic axis shorter than the window revisits faces: count each once
+    use[k] = true;
+    const int fk = wrapi(c[d] + k - 3, n);
+#pragma unroll
+    for (int k2 = 0; k2 < k; ++k2)
+      if (wrapi(c[d] + k2 - 3, n) == fk) use[k] = false;
+    if (flags & HTR_FORCE_TENO) te[k] = true;
+    else if (flags & HTR_FORCE_CENTRAL) te[k] = false;
+    else {
+      const double pa = pp[k + 2], pbv = pp[k + 3];
+      const double psi = fabs(pbv - pa) / fmin(pa, pbv);
+      te[k] = ((fl >> k) & 0x3f) != 0 || psi > psi_c;
+    }
+    al[k] = 0.0;
+    am[k] = 0;
+    if (te[k]) {
+      double best = fabs(ud[k]) + cc[k];
+#pragma unroll
+      for (int mm = 1; mm < 6; ++mm) {
+        const double sp = fabs(ud[k + mm]) + cc[k + mm];
+        if (sp > best) { best = sp; am[k] = mm; }
+      }
+      al[k] = best;
+    }
+    any = any || (te[k] && use[k]);
+  }
+  const double C6[6] = {1.0 / 60.0, -8.0 / 60.0, 37.0 / 60.0, 37.0 / 60.0, -8.0 / 60.0, 1.0 / 60.0};
+  double abar[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double uv[11], f[11];
+    if (any) {
+#pragma unroll
+      for (int o = 0; o < 11; ++o) {
+        uv[o] = U[v * N + qo[o]];
+        f[o] = node_flux<NS>(v, d, uv[o], ud[o], pp[o]);
+      }
+    } else {
+      uv[5] = U[v * N + q];
+    }
+    double lv[7];
+#pragma unroll
+    for (int o = 0; o < 7; ++o) lv[o] = s * lam[v * N + qo[o + 2]];
+    double Fb = 0.0, Ub = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      if (!use[k]) continue;
+      const double g = -xi7[k] * lv[k] + xi7[k + 1] * lv[k + 1];
+      if (!te[k]) {
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm)
+          if (qo[k + mm] == q) Fb += g * C6[mm];
+      } else {
+        double fp[6], fm[6], cp[6], cm[6];
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) {
+          fp[mm] = 0.5 * (f[k + mm] + al[k] * uv[k + mm]);
+          fm[5 - mm] = 0.5 * (f[k + mm] - al[k] * uv[k + mm]);
+        }
+        teno6_coeffs(fp, CT, cp);
+        teno6_coeffs(fm, CT, cm);
+        double da = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) {
+          const double dw = cp[mm] - cm[5 - mm];
+          da += dw * uv[k + mm];
+          if (qo[k + mm] == q) {
+            Fb += g * 0.5 * (cp[mm] + cm[5 - mm]);
+            Ub += g * 0.5 * al[k] * dw;
+          }
+        }
+        abar[k] += g * 0.5 * da;
+      }
+    }
+    // node flux F_v(U_v, u_d, p) at this node
+    const double un = ud[5];
+    Ub += Fb * un;
+    if (v == NS + 3) {
+      pb[PB_U + d] += Fb * (uv[5] + pp[5]);
+      pb[PB_P] += Fb * un;
+    } else {
+      pb[PB_U + d] += Fb * uv[5];
+      if (v == NS + d) pb[PB_P] += Fb;
+    }
+    ubar[v] += Ub;
+  }
+  // Lax-Friedrichs speed: the frozen argmax node receives d(|u_d| + c)
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (!use[k] || !te[k]) continue;
+    if (qo[k + am[k]] == q) {
+      pb[PB_U + d] += abar[k] * (ud[5] < 0.0 ? -1.0 : 1.0);
+      pb[PB_C] += abar[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------- diffusive
+// Face (A, B = A + e_d): adds the cotangent contributions to node A
+// (side = 0) or node B (side = 1).
+template <int NS>
+__device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, const Member& G, int d,
+                                              const int cA[3], long long qA, long long qB, long long N,
+                                              const double* __restrict__ U, const double* __restrict__ T,
+                                              const double* __restrict__ aux, const double* __restrict__ lam,
+                                              double s, int side, double* ubar, double* pb) {
+  constexpr int NV = NS + 4;
+  const double xf = G.xif[d][cA[d]];
+  int cB[3] = {cA[0], cA[1], cA[2]};
+  cB[d] = wrapi(cA[d] + 1, G.n[d]);
+  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  const double xiA = G.xin[d][cA[d]], xiB = G.xin[d][cB[d]];
+  double Gv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Gv[v] = s * (xiA * lam[v * N + qA] - xiB * lam[v * N + qB]);
+  double uA[3], uB[3];
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) {
+    uA[mm] = aux[(4 + mm) * N + qA];
+    uB[mm] = aux[(4 + mm) * N + qB];
+  }
+  double g[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm) g[a][mm] = 0.0;
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) g[d][mm] = xf * (uB[mm] - uA[mm]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == d || !G.act[a]) continue;
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int* cc = sd ? cB : cA;
+      const long long qc = sd ? qB : qA;
+      const long long qp = qc + (long long)(wrapi(cc[a] + 1, G.n[a]) - cc[a]) * strides[a];
+      const long long qm = qc + (long long)(wrapi(cc[a] - 1, G.n[a]) - cc[a]) * strides[a];
+      const double xa = 0.5 * G.xin[a][cc[a]];
+#pragma unroll
+      for (int mm = 0; mm < 3; ++mm) g[a][mm] += 0.5 * (xa * (aux[(4 + mm) * N + qp] - aux[(4 + mm) * N + qm]));
+    }
+  }
+  const double muf = 0.5 * (aux[2 * N + qA] + aux[2 * N + qB]);
+  const double lamf = 0.5 * (aux[3 * N + qA] + aux[3 * N + qB]);
+  const double divu = g[0][0] + g[1][1] + g[2][2];
+  double tau[3], uf[3];
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) {
+    tau[mm] = muf * (g[d][mm] + g[mm][d]);
+    if (mm == d) tau[mm] -= (2.0 / 3.0) * muf * divu;
+    uf[mm] = 0.5 * (uA[mm] + uB[mm]);
+  }
+  double rA = 0.0, rB = 0.0, nA = 0.0, nB = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double a = U[k * N + qA], b = U[k * N + qB];
+    rA += a;
+    rB += b;
+    nA += a * M->iW[k];
+    nB += b * M->iW[k];
+  }
+  const double rhof = 0.5 * (rA + rB);
+  const double Wf = 0.5 * (rA / nA + rB / nB);
+  const double TA = T[qA], TB = T[qB];
+  double term[NS], dX[NS], Df[NS], Yf[NS], J[NS];
+  double corr = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double a = U[k * N + qA], b = U[k * N + qB];
+    Df[k] = 0.5 * (aux[(7 + k) * N + qA] + aux[(7 + k) * N + qB]);
+    dX[k] = xf * (b * M->iW[k] / nB - a * M->iW[k] / nA);
+    term[k] = rhof * Df[k] * (M->W[k] / Wf) * dX[k];
+    corr += term[k];
+    Yf[k] = 0.5 * (a / rA + b / rB);
+  }
+  // ---- reverse
+  const double qnb = -Gv[NS + 3];
+  double taub[3];
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) taub[mm] = Gv[NS + mm] + Gv[NS + 3] * uf[mm];
+  const double lamfb = -qnb * xf * (TB - TA);
+  double TAb = qnb * lamf * xf, TBb = -qnb * lamf * xf;
+  double Jb[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    J[k] = -term[k] + Yf[k] * corr;
+    const double hA = M->RW[k] * TA * hRTs(M, k, TA), hB = M->RW[k] * TB * hRTs(M, k, TB);
+    const double hfb = qnb * J[k];
+    TAb += hfb * 0.5 * M->RW[k] * cpRa(M, k, TA);
+    TBb += hfb * 0.5 * M->RW[k] * cpRa(M, k, TB);
+    Jb[k] = -Gv[k] + qnb * 0.5 * (hA + hB);
+  }
+  double corrb = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) corrb += Jb[k] * Yf[k];
+  double rhofb = 0.0, Wfb = 0.0;
+  double dXb[NS], Yfb[NS], Dfb[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double termb = -Jb[k] + corrb;
+    Yfb[k] = Jb[k] * corr;
+    rhofb += termb * Df[k] * (M->W[k] / Wf) * dX[k];
+    Dfb[k] = termb * rhof * (M->W[k] / Wf) * dX[k];
+    Wfb -= termb * term[k] / Wf;
+    dXb[k] = termb * rhof * Df[k] * M->W[k] / Wf;
+  }
+  double mufb = -(2.0 / 3.0) * taub[d] * divu;
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) mufb += taub[mm] * (g[d][mm] + g[mm][d]);
+  // velocity gradient cotangent, normal row only (tangential rows go to the tangential neighbours)
+  double gdb[3];
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) gdb[mm] = muf * taub[mm];
+  gdb[d] = (4.0 / 3.0) * muf * taub[d];
+  // node-side contributions
+  const double sgn = side ? 1.0 : -1.0;          // d(dX)/dX_B = +xf, d(dX)/dX_A = -xf
+  const double rn = side ? rB : rA, nn = side ? nB : nA;
+  const long long qn = side ? qB : qA;
+  double rbar = 0.5 * Wfb / nn + 0.5 * rhofb;
+  double nbar = -0.5 * Wfb * rn / (nn * nn);
+  double Xn[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double a = U[k * N + qn];
+    Xn[k] = a * M->iW[k] / nn;
+    const double Xb = sgn * dXb[k] * xf;
+    nbar -= Xb * Xn[k] / nn;
+    rbar -= 0.5 * Yfb[k] * a / (rn * rn);
+    ubar[k] += Xb * M->iW[k] / nn + 0.5 * Yfb[k] / rn;
+    pb[PB_D + k] += 0.5 * Dfb[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) ubar[k] += rbar + nbar * M->iW[k];
+  pb[PB_T] += side ? TBb : TAb;
+  pb[PB_MU] += 0.5 * mufb;
+  pb[PB_LAM] += 0.5 * lamfb;
+#pragma unroll
+  for (int mm = 0; mm < 3; ++mm) pb[PB_U + mm] += 0.5 * Gv[NS + 3] * tau[mm] + sgn * xf * gdb[mm];
+}
+
+// Tangential-neighbour contributions: node q is u(A +- e_t) or u(B +- e_t)
+// of the d-face (A, A + e_d).
+template <int NS>
+__device__ __forceinline__ void adj_diff_tangential(const Member& G, int d, int t, const int c[3], long long q,
+                                                    long long N, const double* __restrict__ aux,
+                                                    const double* __restrict__ lam, double s, double* pb) {
+  constexpr int NV = NS + 4;
+  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  // (shift along t, shift along d of A, sign)
+  const int cfg[4][3] = {{-1, 0, 1}, {1, 0, -1}, {-1, -1, 1}, {1, -1, -1}};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int cA[3] = {c[0], c[1], c[2]};
+    cA[t] = wrapi(c[t] + cfg[k][0], G.n[t]);
+    cA[d] = wrapi(c[d] + cfg[k][1], G.n[d]);
+    int cB[3] = {cA[0], cA[1], cA[2]};
+    cB[d] = wrapi(cA[d] + 1, G.n[d]);
+    const long long qA = ((long long)cA[2] * G.n[1] + cA[1]) * G.n[0] + cA[0];
+    const long long qB = ((long long)cB[2] * G.n[1] + cB[1]) * G.n[0] + cB[0];
+    const double xiA = G.xin[d][cA[d]], xiB = G.xin[d][cB[d]];
+    double Gm[3], GE;
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm) Gm[mm] = s * (xiA * lam[(NS + mm) * N + qA] - xiB * lam[(NS + mm) * N + qB]);
+    GE = s * (xiA * lam[(NS + 3) * N + qA] - xiB * lam[(NS + 3) * N + qB]);
+    double taub[3];
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm) taub[mm] = Gm[mm] + GE * 0.5 * (aux[(4 + mm) * N + qA] + aux[(4 + mm) * N + qB]);
+    const double muf = 0.5 * (aux[2 * N + qA] + aux[2 * N + qB]);
+    // g[t][b] += 0.25 xi_t (u_b(node + e_t) - u_b(node - e_t)) for node in {A, B}
+    const double w = cfg[k][2] * 0.25 * G.xin[t][cA[t]];
+    pb[PB_U + d] += w * muf * taub[t];
+    pb[PB_U + t] += w * (-(2.0 / 3.0)) * muf * taub[d];
+  }
+  (void)strides;
+  (void)NV;
+}
+
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_adj_sweep(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                   int nmem, CallArgs A, const double* __restrict__ Ub,
+                                                   const double* __restrict__ Tb, const double* __restrict__ auxb,
+                                                   const unsigned char* __restrict__ flagb,
+                                                   const double* __restrict__ lamb, double s,
+                                                   double* __restrict__ ubdb, double* __restrict__ pbb,
+                                                   double psi_c, double CT) {
+  constexpr int NV = NS + 4, NAUX = 7 + NS, NPB = 8 + NS;
+  const int m = find_member(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const double* U = Ub + NV * G.off;
+  const double* T = Tb + G.off;
+  const double* aux = auxb + NAUX * G.off;
+  const unsigned char* flag = flagb + G.off;
+  const double* lam = lamb + NV * G.off;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  double ubar[NV], pb[NPB];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ubar[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NPB; ++k) pb[k] = 0.0;
+  const unsigned flags = A.flags;
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    adj_conv<NS>(G, d, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
+    if (!(flags & HTR_VISC_OFF)) {
+      int cm[3] = {c[0], c[1], c[2]};
+      cm[d] = wrapi(c[d] - 1, G.n[d]);
+      const long long qm = q + (long long)(cm[d] - c[d]) * strides[d];
+      const long long qp = q + (long long)(wrapi(c[d] + 1, G.n[d]) - c[d]) * strides[d];
+      adj_diff_face<NS>(M, G, d, cm, qm, q, N, U, T, aux, lam, s, 1, ubar, pb);
+      adj_diff_face<NS>(M, G, d, c, q, qp, N, U, T, aux, lam, s, 0, ubar, pb);
+      for (int t = 0; t < 3; ++t)
+        if (t != d && G.act[t]) adj_diff_tangential<NS>(G, d, t, c, q, N, aux, lam, s, pb);
+    }
+  }
+  double* ubd = ubdb + NV * G.off;
+  double* pbo = pbb + NPB * G.off;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ubd[v * N + q] = ubar[v];
+#pragma unroll
+  for (int k = 0; k < NPB; ++k) pbo[k * N + q] = pb[k];
+}
+
+// ------------------------------------------------------------------ point
+// Deterministic block sum of one value per thread; every thread of the block
+// must call it (it contains barriers).
+__device__ __forceinline__ void block_sum_to(double v, double* wred, double* dst) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int w = 0; w < BLK / 64; ++w) a += wred[w];
+    *dst = a;
+  }
+  __syncthreads();
+}
+
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_adj_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                   int nmem, CallArgs A, const double* __restrict__ Ub,
+                                                   const double* __restrict__ Tb, const double* __restrict__ pbb,
+                                                   const double* __restrict__ ubdb, const double* __restrict__ lamb,
+                                                   double s, double h, double* __restrict__ outb,
+                                                   double* __restrict__ thpart, int nth) {
+  constexpr int NV = NS + 4, NPB = 8 + NS;
+  __shared__ double conc[NS][BLK];
+  __shared__ double wred[BLK / 64];
+  const int m = find_member(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const int tid = threadIdx.x;
+  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + tid;
+  const bool live = q < G.N;
+  const long long N = G.N;
+  const unsigned flags = A.flags;
+  const bool chem = !(flags & HTR_CHEM_OFF);
+  const int nr = M->nr;
+  const double* dlnA = A.dlnA ? A.dlnA : G.dlnA;
+  const double* U = Ub + NV * G.off;
+  const double* pbv = pbb + NPB * G.off;
+  const double* ubd = ubdb + NV * G.off;
+  const double* lam = lamb + NV * G.off;
+  double r[NS], Y[NS], X[NS], rb[NS], Yb[NS], Xb[NS], Gs[NS], hRTv[NS], omb_mol[NS], cb[NS];
+  double T = 1000.0, iT = 1e-3, lnT = 0.0, Tbar = 0.0, rho = 1.0, irho = 1.0, E = 0.0, lnP = 0.0;
+  double u[3] = {0.0, 0.0, 0.0}, ub[3] = {0.0, 0.0, 0.0};
+  int ix = 0, jx = 0, kx = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    r[k] = Y[k] = X[k] = rb[k] = Yb[k] = Xb[k] = Gs[k] = hRTv[k] = omb_mol[k] = cb[k] = 0.0;
+  }
+  // ---- phase 1: state, forward quantities, seeds of the chemistry
+  if (live) {
+    rho = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      r[k] = U[k * N + q];
+      rho += r[k];
+      rb[k] = ubd[k * N + q];
+    }
+    irho = 1.0 / rho;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Y[k] = r[k] * irho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      u[a] = U[(NS + a) * N + q] * irho;
+      ub[a] = pbv[(PB_U + a) * N + q];
+    }
+    E = U[(NS + 3) * N + q];
+    T = Tb[G.off + q];
+    iT = 1.0 / T;
+    lnT = log(T);
+    Tbar = pbv[PB_T * N + q];
+    ix = (int)(q % G.n[0]);
+    jx = (int)((q / G.n[0]) % G.n[1]);
+    kx = (int)(q / ((long long)G.n[0] * G.n[1]));
+    if (chem) {
+      const double dV = 1.0 / (G.xin[0][ix] * G.xin[1][jx] * G.xin[2][kx]);
+      const double Hb = h * dV;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        conc[k][tid] = r[k] * M->iW[k];
+        hRTv[k] = hRTa(M, k, T, iT);
+        Gs[k] = hRTv[k] - sRa(M, k, T, lnT);
+      }
+      lnP = log(PREF / (RU * T));
+      double om[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) om[k] = 0.0;
+      for (int j = 0; j < nr; ++j) {
+        double lnkf = M->lnA[j] + M->beta[j] * lnT - M->EaR[j] * iT;
+        if (dlnA) lnkf += dlnA[j];
+        double lnKc = M->dnu[j] * lnP;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) lnKc -= M->nunet[j][k] * Gs[k];
+        double rf = exp(lnkf), rbk = exp(lnkf - lnKc);
+        for (int e = 0; e < M->nre[j]; ++e) {
+          const double cc = conc[M->ridx[j][e]][tid];
+          for (int kk = 0; kk < M->rnu[j][e]; ++kk) rf *= cc;
+        }
+        for (int e = 0; e < M->npr[j]; ++e) {
+          const double cc = conc[M->pidx[j][e]][tid];
+          for (int kk = 0; kk < M->pnu[j][e]; ++kk) rbk *= cc;
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) om[k] += M->nunet[j][k] * (rf - rbk);
+      }
+      // seeds: the source rows of lam, and the heat release -sum h_k wdot_k
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double omk = M->W[k] * om[k];
+        const double hk = M->RW[k] * T * hRTv[k];
+        const double wb = s * lam[k * N + q] - Hb * hk;
+        Tbar += -Hb * omk * M->RW[k] * cpRa(M, k, T);
+        omb_mol[k] = M->W[k] * wb;
+      }
+    }
+  }
+  // ---- phase 2: reverse of the reactions (every thread reaches the block sums)
+  if (chem) {
+    for (int j = 0; j < nr; ++j) {
+      double lnkfb = 0.0;
+      if (live) {
+        double qb = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) qb += M->nunet[j][k] * omb_mol[k];
+        double lnkf = M->lnA[j] + M->beta[j] * lnT - M->EaR[j] * iT;
+        if (dlnA) lnkf += dlnA[j];
+        double lnKc = M->dnu[j] * lnP;
+        double dlnKc = -M->dnu[j] * iT;                       // d lnKc / dT
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          lnKc -= M->nunet[j][k] * Gs[k];
+          dlnKc += M->nunet[j][k] * hRTv[k] * iT;             // d G_k / dT = -hRT_k / T
+        }
+        const double kf = exp(lnkf), kb = exp(lnkf - lnKc);
+        double rf = kf, rbk = kb;
+        for (int e = 0; e < M->nre[j]; ++e) {
+          const double cc = conc[M->ridx[j][e]][tid];
+          for (int kk = 0; kk < M->rnu[j][e]; ++kk) rf *= cc;
+        }
+        for (int e = 0; e < M->npr[j]; ++e) {
+          const double cc = conc[M->pidx[j][e]][tid];
+          for (int kk = 0; kk < M->pnu[j][e]; ++kk) rbk *= cc;
+        }
+        // d(k prod c^nu)/dc_e = k nu_e c_e^(nu_e - 1) prod_{others} c^nu
+        for (int e = 0; e < M->nre[j]; ++e) {
+          double dp = kf * M->rnu[j][e];
+          for (int e2 = 0; e2 < M->nre[j]; ++e2) {
+            const double cc = conc[M->ridx[j][e2]][tid];
+            const int pw = M->rnu[j][e2] - (e2 == e ? 1 : 0);
+            for (int kk = 0; kk < pw; ++kk) dp *= cc;
+          }
+          const int sp = M->ridx[j][e];
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (k == sp) cb[k] += qb * dp;
+        }
+        for (int e = 0; e < M->npr[j]; ++e) {
+          double dp = kb * M->pnu[j][e];
+          for (int e2 = 0; e2 < M->npr[j]; ++e2) {
+            const double cc = conc[M->pidx[j][e2]][tid];
+            const int pw = M->pnu[j][e2] - (e2 == e ? 1 : 0);
+            for (int kk = 0; kk < pw; ++kk) dp *= cc;
+          }
+          const int sp = M->pidx[j][e];
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (k == sp) cb[k] -= qb * dp;
+        }
+        lnkfb = qb * (rf - rbk);
+        const double lnKcb = qb * rbk;
+        Tbar += lnkfb * (M->beta[j] * iT + M->EaR[j] * iT * iT) + lnKcb * dlnKc;
+      }
+      block_sum_to(lnkfb, wred, &thpart[(long long)blockIdx.x * nth + 4 + j]);
+    }
+  } else if (tid == 0) {
+    for (int j = 0; j < nr; ++j) thpart[(long long)blockIdx.x * nth + 4 + j] = 0.0;
+  }
+  // ---- phase 3: transport, EOS, implicit Newton T, conserved variables
+  double thE = 0.0, thx[3] = {0.0, 0.0, 0.0};
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) rb[k] += cb[k] * M->iW[k];
+    double pbar = pbv[PB_P * N + q];
+    const double cbar = pbv[PB_C * N + q];
+    const double mub = pbv[PB_MU * N + q], lamb_ = pbv[PB_LAM * N + q];
+    double iWm = 0.0, cp = 0.0, dcp = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      iWm += Y[k] * M->iW[k];
+      cp += Y[k] * M->RW[k] * cpRa(M, k, T);
+      dcp += Y[k] * M->RW[k] * dcpRa(M, k, T);
+    }
+    const double Wm = 1.0 / iWm;
+    const double p = rho * RU * T * iWm;
+    const double cv = cp - RU * iWm;
+    const double z = cp / cv * p * irho;
+    const double cs = sqrt(z);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) X[k] = Y[k] * Wm * M->iW[k];
+    const double sqT = sqrt(T), T15 = T * sqT;
+    // Bird mixture diffusivities
+    {
+      double Dacc[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) Dacc[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int j = i + 1; j < NS; ++j) {
+          double dd;
+          const double om = om11a(lnT - M->Dlneps[i][j], T * M->Dieps[i][j], iT, M->Dieps[i][j], &dd);
+          const double iD = p * om / (M->Dpre[i][j] * T15);
+          Dacc[i] += fmax(X[j], 0.0) * iD;
+          Dacc[j] += fmax(X[i], 0.0) * iD;
+        }
+      double Daccb[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const double Db = pbv[(PB_D + k) * N + q];
+        if (Dacc[k] < 1e-300) {
+          double dd;
+          const double om = om11a(lnT - M->Dlneps[k][k], T * M->Dieps[k][k], iT, M->Dieps[k][k], &dd);
+          const double Dk = M->Dpre[k][k] * T15 / (p * om);
+          pbar += -Db * Dk / p;
+          Tbar += Db * Dk * (1.5 * iT - dd / om);
+          Daccb[k] = 0.0;
+        } else {
+          const double Dk = (1.0 - Y[k]) / Dacc[k];
+          Yb[k] += -Db / Dacc[k];
+          Daccb[k] = -Db * Dk / Dacc[k];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int j = i + 1; j < NS; ++j) {
+          double dd;
+          const double om = om11a(lnT - M->Dlneps[i][j], T * M->Dieps[i][j], iT, M->Dieps[i][j], &dd);
+          const double iD = p * om / (M->Dpre[i][j] * T15);
+          if (X[j] > 0.0) Xb[j] += Daccb[i] * iD;
+          if (X[i] > 0.0) Xb[i] += Daccb[j] * iD;
+          const double iDb = Daccb[i] * fmax(X[j], 0.0) + Daccb[j] * fmax(X[i], 0.0);
+          pbar += iDb * iD / p;
+          Tbar += iDb * iD * (dd / om - 1.5 * iT);
+        }
+    }
+    // Wilke viscosity and conductivity
+    {
+      double mus[NS], lams[NS], smu[NS], ismu[NS], dlnom[NS], cpk[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        double dd;
+        const double om = om22a(lnT - M->lneps[k], T * M->ieps[k], iT, M->ieps[k], &dd);
+        mus[k] = M->mu_pre[k] * sqT / om;
+        dlnom[k] = dd / om;
+        cpk[k] = M->RW[k] * cpRa(M, k, T) + M->euck[k];
+        lams[k] = mus[k] * cpk[k];
+        smu[k] = sqrt(mus[k]);
+        ismu[k] = 1.0 / smu[k];
+      }
+      double musb[NS], smub[NS], ismub[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) musb[k] = smub[k] = ismub[k] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        double den = 0.0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          const double t1 = 1.0 + smu[i] * ismu[j] * M->wq[i][j];
+          den += X[j] * (t1 * t1 * M->wp[i][j]);
+        }
+        const double id = 1.0 / den;
+        Xb[i] += mub * mus[i] * id + lamb_ * lams[i] * id;
+        musb[i] += mub * X[i] * id;
+        const double lsb = lamb_ * X[i] * id;
+        musb[i] += lsb * cpk[i];
+        Tbar += lsb * mus[i] * M->RW[i] * dcpRa(M, i, T);
+        const double denb = -(mub * X[i] * mus[i] + lamb_ * X[i] * lams[i]) * id * id;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          const double t1 = 1.0 + smu[i] * ismu[j] * M->wq[i][j];
+          Xb[j] += denb * t1 * t1 * M->wp[i][j];
+          const double t1b = denb * X[j] * 2.0 * t1 * M->wp[i][j];
+          smub[i] += t1b * ismu[j] * M->wq[i][j];
+          ismub[j] += t1b * smu[i] * M->wq[i][j];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        smub[k] += -ismub[k] * ismu[k] * ismu[k];
+        musb[k] += smub[k] * 0.5 * ismu[k];
+        Tbar += musb[k] * mus[k] * (0.5 * iT - dlnom[k]);
+      }
+    }
+    // EOS, sound speed, mole fractions
+    double iWmb = 0.0, rhob = 0.0, cpb = 0.0, cvb = 0.0, Wmb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      Yb[k] += Xb[k] * Wm * M->iW[k];
+      Wmb += Xb[k] * Y[k] * M->iW[k];
+    }
+    const double zb = cbar * 0.5 / cs;
+    cpb += zb * p * irho / cv;
+    cvb += -zb * z / cv;
+    pbar += zb * z / p;
+    rhob += -zb * z * irho;
+    cpb += cvb;
+    iWmb += -RU * cvb;
+    rhob += pbar * RU * T * iWm;
+    Tbar += pbar * p * iT;
+    iWmb += pbar * rho * RU * T;
+    iWmb += -Wmb * Wm * Wm;
+    Tbar += cpb * dcp;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Yb[k] += cpb * M->RW[k] * cpRa(M, k, T) + iWmb * M->iW[k];
+    // implicit Newton temperature: e(T, Y) = e with c_v = de/dT
+    const double eb = Tbar / cv;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Yb[k] += -Tbar * M->RW[k] * T * (hRTa(M, k, T, iT) - 1.0) / cv;
+    // e = E / rho - |u|^2 / 2, u = m / rho, Y = r / rho, rho = sum r
+    const double Eb = eb * irho;
+    rhob += -eb * E * irho * irho;
+    double mb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ub[a] += -eb * u[a];
+      mb[a] = ub[a] * irho;
+      rhob += -ub[a] * u[a] * irho;
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      rb[k] += Yb[k] * irho;
+      rhob += -Yb[k] * Y[k] * irho;
+    }
+    double* out = outb + NV * G.off;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) out[k * N + q] += rb[k] + rhob;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[(NS + a) * N + q] += ubd[(NS + a) * N + q] + mb[a];
+    out[(NS + 3) * N + q] += ubd[(NS + 3) * N + q] + Eb;
+    // laser parameters: q_L = E norm prod_a G_a exp(-((t - t0)/st)^2 / 2)
+    const LaserDev& L = A.use_call_laser ? A.laser : G.laser;
+    if (L.on) {
+      const double tk = (A.t_dev ? A.t_dev[m] : A.t) + (A.dt_dev ? A.tcoef * A.dt_dev[m] : 0.0);
+      const double tt = (tk - L.t0) / L.st;
+      const double tf = exp(-0.5 * tt * tt);
+      const int cidx[3] = {ix, jx, kx};
+      double Ga[3], dGa[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Ga[a] = 1.0;
+        dGa[a] = 0.0;
+        if (!G.act[a]) continue;
+        const double Lp = G.L[a];
+        double rr = G.xnode[a][cidx[a]] - L.xc[a];
+        rr -= Lp * rint(rr / Lp);
+        double g = 0.0, dg = 0.0;
+        for (int mm = -L.M[a]; mm <= L.M[a]; ++mm) {
+          const double zz = (rr - mm * Lp) / L.sr;
+          const double ex = exp(-0.5 * zz * zz);
+          g += ex;
+          dg += ex * zz / L.sr;          // d/d(centre) of exp(-zz^2/2)
+        }
+        Ga[a] = g;
+        dGa[a] = dg;
+      }
+      const double qLb = s * lam[(NS + 3) * N + q];
+      const double base = L.norm * tf;
+      thE = qLb * base * Ga[0] * Ga[1] * Ga[2];
+      thx[0] = qLb * L.E * base * dGa[0] * Ga[1] * Ga[2];
+      thx[1] = qLb * L.E * base * Ga[0] * dGa[1] * Ga[2];
+      thx[2] = qLb * L.E * base * Ga[0] * Ga[1] * dGa[2];
+    }
+  }
+  // ---- phase 4: laser parameter partials (every thread)
+  block_sum_to(thE, wred, &thpart[(long long)blockIdx.x * nth + 0]);
+  block_sum_to(thx[0], wred, &thpart[(long long)blockIdx.x * nth + 1]);
+  block_sum_to(thx[1], wred, &thpart[(long long)blockIdx.x * nth + 2]);
+  block_sum_to(thx[2], wred, &thpart[(long long)blockIdx.x * nth + 3]);
+}
+
+// One block per member: fixed-order sums of the parameter partials.
+__global__ __launch_bounds__(BLK) void k_adj_theta(const Member* __restrict__ mem, const double* __restrict__ thpart,
+                                                   int nth, double* __restrict__ pbar) {
+  __shared__ double sh[BLK];
+  const Member& G = mem[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int i = 0; i < nth; ++i) {
+    double a = 0.0;
+    for (int k = tid; k < G.nblocks; k += BLK) a += thpart[(long long)(G.block_begin + k) * nth + i];
+    sh[tid] = a;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+      if (tid < o) sh[tid] += sh[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) pbar[(long long)blockIdx.x * nth + i] += sh[0];
+    __syncthreads();
+  }
+}
+
+// y = a x + b y over n doubles (b = 0: y = a x)
+__global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+template <int NS>
+static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                        const double* U, const double* T, const double* aux, const unsigned char* flag,
+                        const double* lam, double s, double h, double* ubd, double* pbv, double* out,
+                        double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_sweep<NS>, dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam, s, ubd,
+                     pbv, psi_c, CT);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_point<NS>, dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, pbv, ubd, lam, s, h, out,
+                     thpart, nth);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                          const double* U, const double* T, const double* aux, const unsigned char* flag,
+                          const double* lam, double s, double h, double* ubd, double* pbv, double* out,
+                          double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
+#define C_(NS) adj_t<NS>(M, mem, nmem, nblocks, a, U, T, aux, flag, lam, s, h, ubd, pbv, out, thpart, nth, psi_c, CT, st)
+  switch (ns) {
+    case 1: return C_(1); case 2: return C_(2); case 3: return C_(3);
+    case 4: return C_(4); case 5: return C_(5); case 6: return C_(6);
+    case 7: return C_(7); case 8: return C_(8); case 9: return C_(9);
+    case 10: return C_(10); case 11: return C_(11); case 12: return C_(12);
+    default: return hipErrorInvalidValue;
+  }
+#undef C_
+}
+
+hipError_t launch_adj_theta(const Member* mem, int nmem, const double* thpart, int nth, double* pbar,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_theta, dim3(nmem), dim3(BLK), 0, st, mem, thpart, nth, pbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+}  // namespace htr

@@ -113,5 +113,12 @@ hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);
+hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                          const double* U, const double* T, const double* aux, const unsigned char* flag,
+                          const double* lam, double s, double h, double* ubd, double* pbv, double* out,
+                          double* thpart, int nth, double psi_c, double CT, hipStream_t st);
+hipError_t launch_adj_theta(const Member* mem, int nmem, const double* thpart, int nth, double* pbar,
+                            hipStream_t st);
+hipError_t launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);
 
 }  // namespace htr

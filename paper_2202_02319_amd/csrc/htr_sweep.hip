@@ -16,57 +16,10 @@
 #include <math.h>
 
 #include "htr_dev.h"
+#include "htr_flux.h"
 
 namespace htr {
 
-__device__ __forceinline__ double hRTs(const MechTables* __restrict__ M, int s, double T) {
-  const double* a = M->hc[s];
-  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5] / T;
-}
-
-// TENO6 reconstruction at x_{i+1/2} from f[0..5] = f_{i-2..i+3}.
-__device__ __forceinline__ double teno6(const double f[6], double CT) {
-  const double q0 = (-f[1] + 5.0 * f[2] + 2.0 * f[3]) * (1.0 / 6.0);
-  const double q1 = (2.0 * f[2] + 5.0 * f[3] - f[4]) * (1.0 / 6.0);
-  const double q2 = (2.0 * f[0] - 7.0 * f[1] + 11.0 * f[2]) * (1.0 / 6.0);
-  const double q3 = (3.0 * f[2] + 13.0 * f[3] - 5.0 * f[4] + f[5]) * (1.0 / 12.0);
-  const double s0a = f[1] - 2.0 * f[2] + f[3], s0b = f[1] - f[3];
-  const double s1a = f[2] - 2.0 * f[3] + f[4], s1b = 3.0 * f[2] - 4.0 * f[3] + f[4];
-  const double s2a = f[0] - 2.0 * f[1] + f[2], s2b = f[0] - 4.0 * f[1] + 3.0 * f[2];
-  const double s3a = -11.0 * f[2] + 18.0 * f[3] - 9.0 * f[4] + 2.0 * f[5];
-  const double s3b = 2.0 * f[2] - 5.0 * f[3] + 4.0 * f[4] - f[5];
-  const double s3c = -f[2] + 3.0 * f[3] - 3.0 * f[4] + f[5];
-  const double b0 = (13.0 / 12.0) * s0a * s0a + 0.25 * s0b * s0b;
-  const double b1 = (13.0 / 12.0) * s1a * s1a + 0.25 * s1b * s1b;
-  const double b2 = (13.0 / 12.0) * s2a * s2a + 0.25 * s2b * s2b;
-  const double b3 = (1.0 / 36.0) * s3a * s3a + (13.0 / 12.0) * s3b * s3b + (781.0 / 720.0) * s3c * s3c;
-  // six-point polynomial coefficients (origin at the centre of cell i)
-  const double a1 = (341.0 * f[0] - 2785.0 * f[1] - 2590.0 * f[2] + 6670.0 * f[3] - 1895.0 * f[4] + 259.0 * f[5]) *
-                    (1.0 / 5760.0);
-  const double a2 = -(f[0] - 12.0 * f[1] + 22.0 * f[2] - 12.0 * f[3] + f[4]) * (1.0 / 16.0);
-  const double a3 = -(5.0 * f[0] + 11.0 * f[1] - 70.0 * f[2] + 94.0 * f[3] - 47.0 * f[4] + 7.0 * f[5]) *
-                    (1.0 / 144.0);
-  const double a4 = (f[0] - 4.0 * f[1] + 6.0 * f[2] - 4.0 * f[3] + f[4]) * (1.0 / 24.0);
-  const double a5 = -(f[0] - 5.0 * f[1] + 10.0 * f[2] - 10.0 * f[3] + 5.0 * f[4] - f[5]) * (1.0 / 120.0);
-  const double b6 = a1 * (a1 + 0.5 * a3 + 0.125 * a5) + a2 * ((13.0 / 3.0) * a2 + (21.0 / 5.0) * a4) +
-                    a3 * ((3129.0 / 80.0) * a3 + (14127.0 / 224.0) * a5) + (87617.0 / 140.0) * a4 * a4 +
-                    (252337135.0 / 16128.0) * a5 * a5;
-  const double tau = fabs(b6 - (b1 + b2 + 4.0 * b0) * (1.0 / 6.0));
-  const double r0 = 1.0 + tau / (b0 + 1e-40), r1 = 1.0 + tau / (b1 + 1e-40);
-  const double r2 = 1.0 + tau / (b2 + 1e-40), r3 = 1.0 + tau / (b3 + 1e-40);
-  const double irm = 1.0 / fmax(fmax(r0, r1), fmax(r2, r3));
-  double g0 = r0 * irm, g1 = r1 * irm, g2 = r2 * irm, g3 = r3 * irm;
-  g0 = g0 * g0 * g0; g0 *= g0;
-  g1 = g1 * g1 * g1; g1 *= g1;
-  g2 = g2 * g2 * g2; g2 *= g2;
-  g3 = g3 * g3 * g3; g3 *= g3;
-  const double igs = 1.0 / (g0 + g1 + g2 + g3);
-  const double w0 = (g0 * igs >= CT) ? 9.0 / 20.0 : 0.0;
-  const double w1 = (g1 * igs >= CT) ? 3.0 / 10.0 : 0.0;
-  const double w2 = (g2 * igs >= CT) ? 1.0 / 20.0 : 0.0;
-  const double w3 = (g3 * igs >= CT) ? 1.0 / 5.0 : 0.0;
-  return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
-}
 
 // Convective contribution of direction d to acc[] (minus the flux difference).
 template <int NS>
@@ -119,9 +72,7 @@ __device__ __forceinline__ void conv_dir(const Member& G, int d, const int c[3],
 #pragma unroll
     for (int o = 0; o < 7; ++o) {
       uv[o] = U[v * N + qo[o]];
-      if (v == NS + 3) f[o] = (uv[o] + pp[o]) * ud[o];
-      else if (v == NS + d) f[o] = uv[o] * ud[o] + pp[o];
-      else f[o] = uv[o] * ud[o];
+      f[o] = node_flux<NS>(v, d, uv[o], ud[o], pp[o]);
     }
     double F[2];
 #pragma unroll

@@ -171,6 +171,29 @@ def htr_timing_read(ctx):
     return {KERNEL_CLASSES[k]: (ms[k], n[k]) for k in range(4)}
 
 
+def htr_adjoint_work_bytes(ctx):
+    return int(ctx.lib.htr_adjoint_work_bytes(ctx.h))
+
+
+def new_adjoint_work(ctx, device="cuda"):
+    return torch.empty(htr_adjoint_work_bytes(ctx) // 8, dtype=torch.float64, device=device)
+
+
+def htr_rhs_adjoint(ctx, U, T_io, t, laser, dlnA_dev, lam, s, h, Ubar_acc, pbar_acc, adj_work, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rhs_adjoint(ctx.h, _ptr(U), _ptr(T_io), float(t), C.byref(L) if L else None, _ptr(dlnA_dev),
+                                  _ptr(lam), float(s), float(h), _ptr(Ubar_acc), _ptr(pbar_acc), _ptr(adj_work),
+                                  _stream(stream)))
+
+
+def htr_rk3_step_adjoint(ctx, Un, stages, T_io, t, dt, laser, dlnA_dev, Jbar, Ubar, pbar_acc, adj_work,
+                         stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rk3_step_adjoint(ctx.h, _ptr(Un), _ptr(stages), _ptr(T_io), float(t), float(dt),
+                                       C.byref(L) if L else None, _ptr(dlnA_dev), float(Jbar), _ptr(Ubar),
+                                       _ptr(pbar_acc), _ptr(adj_work), _stream(stream)))
+
+
 def htr_check(ctx, stream=None):
     check(ctx.lib.htr_check(ctx.h, _stream(stream)))
 
