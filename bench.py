@@ -148,6 +148,43 @@ def ensemble_measure(steps, warm=1):
             "per_member_ms_per_step": 1e3 * t_m / steps}
 
 
+def adjoint_measure(nsteps=50, every=10, n=64):
+    """The adjoint workload: the 64^3 mixing layer, `nsteps` RK3 steps with a
+    frozen dt, checkpoints every `every` steps; gradient of the time-
+    integrated heat release with respect to (E, centre, ln A_1..20).
+    Returns forward time (with checkpointing) and backward time (segment
+    re-runs + reverse sweep) and their ratio."""
+    import torch
+    import synth
+    from paper_2202_02319_amd import htr
+    from paper_2202_02319_amd.adjoint import HeatReleaseProblem
+    case = synth.case_c5(n=n, steps=nsteps)
+    ctx = htr.Context.from_case(case)
+    U0 = htr.cons_from_case(ctx, case)
+    T0 = htr.to_dev(case.T)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    htr.htr_stable_dt(ctx, U0, T0.clone(), dt)
+    prob = HeatReleaseProblem(ctx, U0, T0, case.laser, float(dt.item()), nsteps, checkpoint_every=every)
+    theta = torch.tensor([case.laser.E, *case.laser.center] + [0.0] * case.mech.nr, dtype=torch.float64,
+                         device="cuda")
+    J, ck = prob.forward(theta)            # warm-up
+    prob.backward(theta, ck)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, ck = prob.forward(theta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g, _ = prob.backward(theta, ck)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gh = g.cpu().numpy()
+    return {"workload": f"{n}^3 mixing layer, {nsteps} RK3 steps, frozen dt, checkpoints every {every}; "
+                        "dJ/d(E, centre, ln A_1..20)",
+            "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+            "adjoint_over_forward": (t2 - t1) / (t1 - t0), "J": float(J.item()),
+            "dJ_dE": float(gh[0]), "dJ_dcentre": [float(v) for v in gh[1:4]]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +194,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
+    ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (ensemble members or grid blocks "
@@ -248,6 +286,9 @@ def main():
         del U, T, work
         torch.cuda.empty_cache()
         out["ensemble"] = ensemble_measure(args.ens_steps)
+    if args.adj_steps > 0:
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_measure(args.adj_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -52,7 +52,8 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
   a.flags = c->scheme.flags;
   HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
                       c->ws.status, 0, st));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, C.scheme.theta_c, nullptr, st));
+  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, nullptr,
+                       st));
   const int nth = 4 + c->nr;
   HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T, c->ws.aux, c->ws.flag, lam, s, h, b.ubd, b.pb,
                         out, b.thpart, nth, C.scheme.psi_c, C.scheme.teno_CT, st));

@@ -25,6 +25,7 @@ struct htr_batch {
   double* ddlnA = nullptr;
   long long Ntot = 0;
   int nblocks = 0;
+  int ntblocks = 0;
   Workspace ws;
   Timer timer;
   hipStream_t gstream = nullptr;   // capture/replay stream (default priority)
@@ -42,6 +43,7 @@ static Ctx bview(const htr_batch* b) {
   v.mem = b->dmem;
   v.nmem = b->nmem;
   v.nblocks = b->nblocks;
+  v.ntblocks = b->ntblocks;
   v.scheme = b->ctx->scheme;
   v.total_cells = b->Ntot;
   v.timer = const_cast<Timer*>(&b->timer);
@@ -92,6 +94,11 @@ htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* m
     M.off = off;
     M.block_begin = blocks;
     M.nblocks = (int)((N + BLK - 1) / BLK);
+    for (int a = 0; a < 3; ++a) {
+      M.n[a] = d.n[a];
+      M.act[a] = d.n[a] > 1;
+    }
+    set_tiles(M, &b->ntblocks);
     b->offs[m] = off;
     off += N;
     blocks += M.nblocks;

@@ -108,6 +108,7 @@ htr_status build_tables(const htr_mech_desc* m, MechTables* T) {
     T->mu_pre[s] = (5.0 / 16.0) * std::sqrt(PI * mass * KB) / (PI * sg * sg);
     T->ieps[s] = 1.0 / ek;
     T->lneps[s] = std::log(ek);
+    T->pw22[s] = std::pow(ek, 0.14874);
     T->euck[s] = 1.25 * RU / W;
   }
   for (int i = 0; i < ns; ++i)
@@ -121,6 +122,8 @@ htr_status build_tables(const htr_mech_desc* m, MechTables* T) {
       T->Dpre[i][j] = (3.0 / 16.0) * std::sqrt(2.0 * PI * KB * KB * KB / mij) / (PI * sg * sg);
       T->Dieps[i][j] = 1.0 / ek;
       T->Dlneps[i][j] = std::log(ek);
+      T->pw11[i][j] = std::pow(ek, 0.15610);
+      T->iDpre[i][j] = 1.0 / T->Dpre[i][j];
     }
   for (int j = 0; j < m->nr; ++j) {
     if (!std::isfinite(m->lnA[j]) || !std::isfinite(m->beta[j]) || !std::isfinite(m->Ea[j]))
@@ -166,6 +169,8 @@ htr_status ws_alloc(Workspace& w, int ns, long long N, int nblocks, int nmem) {
   if ((e = hipMalloc(&w.aux, sizeof(double) * naux * N)) != hipSuccess ||
       (e = hipMalloc(&w.src, sizeof(double) * (ns + 1) * N)) != hipSuccess ||
       (e = hipMalloc(&w.flag, (size_t)N)) != hipSuccess ||
+      (e = hipMalloc(&w.grad, sizeof(double) * 9 * N)) != hipSuccess ||
+      (e = hipMalloc(&w.part, sizeof(double) * (ns + 4) * N)) != hipSuccess ||
       (e = hipMalloc(&w.blkred, sizeof(double) * 2 * (size_t)nblocks)) != hipSuccess ||
       (e = hipMalloc(&w.status, sizeof(unsigned))) != hipSuccess ||
       (e = hipMalloc(&w.scal, sizeof(double) * 2 * (size_t)nmem)) != hipSuccess)
@@ -180,6 +185,8 @@ void ws_free(Workspace& w) {
   hipFree(w.aux);
   hipFree(w.src);
   hipFree(w.flag);
+  hipFree(w.grad);
+  hipFree(w.part);
   hipFree(w.blkred);
   hipFree(w.status);
   hipFree(w.scal);
@@ -242,12 +249,12 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   }
   {
     TimedLaunch tl(C.timer, 1, s);
-    HIP_OK(launch_sensor(C.mem, C.nmem, C.nblocks, w.aux, C.ns, w.flag, C.scheme.theta_c, nullptr, s));
+    HIP_OK(launch_sensor(C.mem, C.nmem, C.nblocks, w.aux, C.ns, w.flag, w.grad, C.scheme.theta_c, nullptr, s));
   }
   {
     TimedLaunch tl(C.timer, 2, s);
-    HIP_OK(launch_sweep(C.ns, C.M, C.mem, C.nmem, C.nblocks, a, U, Un, T, w.aux, w.src, w.flag, out, ca, cb,
-                        rhs_only, C.scheme.psi_c, C.scheme.teno_CT, s));
+    HIP_OK(launch_sweep(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, Un, T, w.aux, w.src, w.flag, w.grad, w.part,
+                        out, ca, cb, rhs_only, C.scheme.psi_c, C.scheme.teno_CT, s));
   }
   return HTR_OK;
 }
@@ -291,6 +298,7 @@ static Ctx view(const htr_ctx* c) {
   v.mem = c->dmem;
   v.nmem = 1;
   v.nblocks = c->nblocks;
+  v.ntblocks = c->ntblocks;
   v.scheme = c->scheme;
   v.total_cells = c->N;
   for (int a = 0; a < 3; ++a) {
@@ -380,6 +388,7 @@ htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, cons
   M.off = 0;
   M.block_begin = 0;
   M.nblocks = c->nblocks;
+  set_tiles(M, &c->ntblocks);
   M.laser.on = 0;
   M.dlnA = nullptr;
   if ((e = hipMalloc(&c->dmem, sizeof(Member))) != hipSuccess)
@@ -452,7 +461,7 @@ htr_status htr_cells(htr_ctx* c, const double* U, double* T_io, double t, const 
   hipStream_t s = (hipStream_t)stream;
   HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T_io, c->ws.aux, c->ws.src, nullptr, nullptr, out,
                       c->ws.status, 0, s));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, C.scheme.theta_c, out, s));
+  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, out, s));
   return HTR_OK;
 }
 

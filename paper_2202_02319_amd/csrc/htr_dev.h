@@ -38,6 +38,9 @@ struct MechTables {
   double wp[MAXNS][MAXNS];                 // 1 / sqrt(8 (1 + W_i / W_j))
   double Dpre[MAXNS][MAXNS];               // D_ij = Dpre T^(3/2) / (p Omega11(T/eps_ij))
   double Dieps[MAXNS][MAXNS], Dlneps[MAXNS][MAXNS];
+  double pw22[MAXNS];                      // (eps/k)^0.14874: T*^-0.14874 = T^-0.14874 pw22
+  double pw11[MAXNS][MAXNS];               // eps_ij^0.15610
+  double iDpre[MAXNS][MAXNS];              // 1 / Dpre
   double lnA[MAXNR], beta[MAXNR], EaR[MAXNR], dnu[MAXNR];
   double nunet[MAXNR][MAXNS];              // nu'' - nu'
   int nre[MAXNR], npr[MAXNR];              // distinct reactant / product species
@@ -62,6 +65,10 @@ struct Member {
   long long off;              // cell offset in packed arrays
   int block_begin;            // first block of this member in per-cell launches
   int nblocks;
+  int tdim[3];                // tile of the tiled flux kernels (256 cells)
+  int ntile[3];               // tiles per axis
+  int tblock_begin;           // first block of this member in tiled launches
+  int ntblocks;
   const double* xin[3];       // d(xi)/dx at nodes
   const double* xif[3];       // d(xi)/dx at faces i+1/2
   const double* xnode[3];     // node coordinates
@@ -91,6 +98,28 @@ __device__ __forceinline__ int find_member(const Member* __restrict__ mem, int n
   return lo;
 }
 
+// Member of a block in the tiled launches.
+__device__ __forceinline__ int find_member_tiled(const Member* __restrict__ mem, int nmem, int b) {
+  int lo = 0, hi = nmem - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (mem[mid].tblock_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tile origin of local tiled block bl.  Blocks are dealt to the eight XCDs
+// round-robin; the first 8*(nb/8) blocks are remapped so that each XCD works
+// on one contiguous run of tiles and neighbouring tiles share its L2.
+__device__ __forceinline__ void tile_origin(const Member& G, int bl, int o[3]) {
+  const int nb = G.ntblocks, per = nb >> 3;
+  const int lb = bl < 8 * per ? (bl & 7) * per + (bl >> 3) : bl;
+  const int tx = lb % G.ntile[0], ty = (lb / G.ntile[0]) % G.ntile[1], tz = lb / (G.ntile[0] * G.ntile[1]);
+  o[0] = tx * G.tdim[0];
+  o[1] = ty * G.tdim[1];
+  o[2] = tz * G.tdim[2];
+}
+
 __device__ __forceinline__ int wrapi(int i, int n) {
   i = i % n;
   return i < 0 ? i + n : i;
@@ -105,11 +134,13 @@ hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem
                         const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
                         double* cells_out, unsigned* status, int want_dt, hipStream_t s);
 hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
-                         double theta_c, double* theta_out, hipStream_t s);
-hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+                         double* grad, double theta_c, double* theta_out, hipStream_t s);
+hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
                         const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                        const unsigned char* flag, double* out, double ca, double cb, int rhs_only,
-                        double psi_c, double CT, hipStream_t s);
+                        const unsigned char* flag, const double* grad, double* part, double* out, double ca,
+                        double cb, int rhs_only, double psi_c, double CT, hipStream_t s);
+// tile shape and tiled-block count of a member (host side)
+void set_tiles(Member& M, int* tblocks);
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);

@@ -83,6 +83,11 @@ __device__ __forceinline__ double node_flux(int v, int d, double U, double ud, d
   return U * ud;
 }
 
+__device__ __forceinline__ double hRTi(const MechTables* __restrict__ M, int s, double T, double iT) {
+  const double* a = M->hc[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5] * iT;
+}
+
 __device__ __forceinline__ double hRTs(const MechTables* __restrict__ M, int s, double T) {
   const double* a = M->hc[s];
   return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + a[5] / T;

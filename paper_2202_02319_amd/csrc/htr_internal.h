@@ -26,6 +26,8 @@ struct Workspace {
   double* aux = nullptr;          // [7 + ns][N]
   double* src = nullptr;          // [ns + 1][N]
   unsigned char* flag = nullptr;  // [N]
+  double* grad = nullptr;         // [9][N] nodal velocity gradient d u_m / d x_a (row 3a + m)
+  double* part = nullptr;         // [nv][N] sources + convective flux differences of a stage
   double* blkred = nullptr;       // [2][nblocks]
   unsigned* status = nullptr;
   double* scal = nullptr;         // [2][nmem] scratch scalars
@@ -59,6 +61,7 @@ struct Ctx {
   const Member* mem = nullptr;
   int nmem = 1;
   int nblocks = 0;
+  int ntblocks = 0;               // tiled launches
   htr_scheme scheme{};
   long long total_cells = 0;
   int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
@@ -92,6 +95,7 @@ struct htr_ctx {
   double L[3] = {0, 0, 0};
   long long N = 0;
   int nblocks = 0;
+  int ntblocks = 0;
   htr::Workspace ws;
   htr::Timer timer;
 };

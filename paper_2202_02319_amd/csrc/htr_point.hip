@@ -185,13 +185,16 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
 #pragma unroll
     for (int s = 0; s < NS; ++s) X[s] = Y[s] * Wm * M->iW[s];
 
-    // ---- transport
+    // ---- transport.  The power terms of the collision integrals factor:
+    // (T/eps)^-b = T^-b eps^b, one exponential per cell for each fit.
     const double lnT = log(T), sqT = sqrt(T);
+    const double Tb22 = exp(-0.14874 * lnT), Tb11 = exp(-0.15610 * lnT);
     double mus[NS], lams[NS], smu[NS], ismu[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double Ts = T * M->ieps[s];
-      mus[s] = M->mu_pre[s] * sqT / om22(lnT - M->lneps[s], Ts);
+      const double o22 = 1.16145 * (Tb22 * M->pw22[s]) + 0.52487 * exp(-0.77320 * Ts) + 2.16178 * exp(-2.43787 * Ts);
+      mus[s] = M->mu_pre[s] * sqT / o22;
       lams[s] = mus[s] * (M->RW[s] * cpR(M, s, T) + M->euck[s]);
       smu[s] = sqrt(mus[s]);
       ismu[s] = 1.0 / smu[s];
@@ -212,13 +215,15 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
     double Dacc[NS], Ds[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) Dacc[s] = 0.0;
-    const double T15 = T * sqT;
+    const double T15 = T * sqT, pT15 = p / T15;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
 #pragma unroll
       for (int j = i + 1; j < NS; ++j) {
         const double Ts = T * M->Dieps[i][j];
-        const double iD = p * om11(lnT - M->Dlneps[i][j], Ts) / (M->Dpre[i][j] * T15);
+        const double o11 = 1.06036 * (Tb11 * M->pw11[i][j]) + 0.19300 * exp(-0.47635 * Ts) +
+                           1.03587 * exp(-1.52996 * Ts) + 1.76474 * exp(-3.89411 * Ts);
+        const double iD = pT15 * o11 * M->iDpre[i][j];
         Dacc[i] += fmax(X[j], 0.0) * iD;
         Dacc[j] += fmax(X[i], 0.0) * iD;
       }
@@ -355,11 +360,12 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
 
 // ----------------------------------------------------------------- sensor
 // theta = (div u)^2 / ((div u)^2 + |curl u|^2 + 1e-300) with second-order
-// central differences; flag = theta > theta_c.
+// central differences; flag = theta > theta_c.  Also stores the nodal
+// velocity gradient (the tangential derivatives of the diffusive fluxes).
 __global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, int nmem,
                                                 const double* __restrict__ auxb, int naux,
-                                                unsigned char* __restrict__ flagb, double theta_c,
-                                                double* __restrict__ theta_out, int nq) {
+                                                unsigned char* __restrict__ flagb, double* __restrict__ gradb,
+                                                double theta_c, double* __restrict__ theta_out, int nq) {
   const int m = find_member(mem, nmem, blockIdx.x);
   const Member& G = mem[m];
   const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
@@ -379,6 +385,13 @@ __global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, 
     const double xi = G.xin[a][c[a]];
 #pragma unroll
     for (int mm = 0; mm < 3; ++mm) g[a][mm] = xi * (vel[mm * N + qp] - vel[mm * N + qm]) / 2.0;
+  }
+  if (gradb) {
+    double* grad = gradb + 9 * G.off;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int mm = 0; mm < 3; ++mm) grad[(3 * a + mm) * N + q] = g[a][mm];
   }
   const double div = g[0][0] + g[1][1] + g[2][2];
   const double wx = g[1][2] - g[2][1], wy = g[2][0] - g[0][2], wz = g[0][1] - g[1][0];
@@ -471,9 +484,9 @@ hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem
 }
 
 hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
-                         double theta_c, double* theta_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, nmem, aux, 7 + ns, flag, theta_c, theta_out,
-                     5 + 2 * ns + 3);
+                         double* grad, double theta_c, double* theta_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, nmem, aux, 7 + ns, flag, grad, theta_c,
+                     theta_out, 5 + 2 * ns + 3);
   return hipGetLastError();
 }
 

@@ -8,10 +8,10 @@
 // second-order central differences for the diffusive fluxes; Sec. 5.1 eqs.
 // (1)-(3), (5), (6) for the flux vectors.
 //
-// One thread per cell; each thread evaluates the two faces of its cell in
-// each direction (the same face is evaluated bit-identically by both of its
-// cells, so the scheme stays exactly conservative).  Node data come through
-// the L1/L2 caches.
+// Two tiled kernels per stage, one block per 256-cell tile: k_conv (sources
+// and convective flux differences, with the tile and its halo staged in
+// LDS) and k_diff (diffusive flux differences and the stage update).  Every
+// face is evaluated once, so the scheme is exactly conservative.
 
 #include <math.h>
 
@@ -21,95 +21,225 @@
 namespace htr {
 
 
-// Convective contribution of direction d to acc[] (minus the flux difference).
-template <int NS>
-__device__ __forceinline__ void conv_dir(const Member& G, int d, const int c[3], long long q, long long N,
-                                         const double* __restrict__ U, const double* __restrict__ aux,
-                                         const unsigned char* __restrict__ flag, unsigned flags, double psi_c,
-                                         double CT, double* acc) {
-  constexpr int NV = NS + 4;
-  const int n = G.n[d];
-  const long long stride = d == 0 ? 1 : (d == 1 ? (long long)G.n[0] : (long long)G.n[0] * G.n[1]);
-  long long qo[7];
-  double ud[7], pp[7], cc[7];
-  int fl = 0;
-#pragma unroll
-  for (int o = 0; o < 7; ++o) {
-    qo[o] = q + (long long)(wrapi(c[d] + o - 3, n) - c[d]) * stride;
-    ud[o] = aux[(4 + d) * N + qo[o]];
-    pp[o] = aux[qo[o]];
-    cc[o] = aux[N + qo[o]];
-    fl |= (int)flag[qo[o]] << o;
-  }
-  // face L = c-1/2 uses nodes o = 0..5, face R = c+1/2 uses o = 1..6
-  bool tL, tR;
-  if (flags & HTR_FORCE_TENO) {
-    tL = tR = true;
-  } else if (flags & HTR_FORCE_CENTRAL) {
-    tL = tR = false;
+// Tile shape of the tiled kernels: 256 cells, 16 x 4 x 4 on 3-D grids,
+// 16 x 16 over the two active axes of 2-D grids, 256 along a 1-D grid.
+void set_tiles(Member& M, int* tblocks) {
+  int act[3] = {M.act[0], M.act[1], M.act[2]};
+  const int na = act[0] + act[1] + act[2];
+  int t[3] = {1, 1, 1};
+  if (na == 3) {
+    t[0] = 16; t[1] = 4; t[2] = 4;
+  } else if (na == 2) {
+    for (int a = 0; a < 3; ++a) t[a] = act[a] ? 16 : 1;
+  } else if (na == 1) {
+    for (int a = 0; a < 3; ++a) t[a] = act[a] ? 256 : 1;
   } else {
-    const double psiL = fabs(pp[3] - pp[2]) / fmin(pp[2], pp[3]);
-    const double psiR = fabs(pp[4] - pp[3]) / fmin(pp[3], pp[4]);
-    tL = (fl & 0x3f) != 0 || psiL > psi_c;
-    tR = (fl & 0x7e) != 0 || psiR > psi_c;
+    t[0] = 256;
   }
-  double aL = 0.0, aR = 0.0;
-  if (tL || tR) {
-    double sp[7];
-#pragma unroll
-    for (int o = 0; o < 7; ++o) sp[o] = fabs(ud[o]) + cc[o];
-    aL = sp[0];
-#pragma unroll
-    for (int o = 1; o < 6; ++o) aL = fmax(aL, sp[o]);
-    aR = sp[1];
-#pragma unroll
-    for (int o = 2; o < 7; ++o) aR = fmax(aR, sp[o]);
+  int nb = 1;
+  for (int a = 0; a < 3; ++a) {
+    M.tdim[a] = t[a];
+    M.ntile[a] = (M.n[a] + t[a] - 1) / t[a];
+    nb *= M.ntile[a];
   }
-  const double xi = G.xin[d][c[d]];
+  M.tblock_begin = *tblocks;
+  M.ntblocks = nb;
+  *tblocks += nb;
+}
+
+// TENO6 face flux on the local Lax-Friedrichs split, kept out of line so the
+// (far more common) central faces do not carry its register footprint.
+__device__ __attribute__((noinline)) double teno_face(double f0, double f1, double f2, double f3, double f4,
+                                                     double f5, double u0, double u1, double u2, double u3,
+                                                     double u4, double u5, double al, double CT) {
+  const double f6[6] = {f0, f1, f2, f3, f4, f5}, u6[6] = {u0, u1, u2, u3, u4, u5};
+  double fp[6], fm[6];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double uv[7], f[7];
+  for (int mm = 0; mm < 6; ++mm) {
+    fp[mm] = 0.5 * (f6[mm] + al * u6[mm]);
+    fm[5 - mm] = 0.5 * (f6[mm] - al * u6[mm]);
+  }
+  return teno6(fp, CT) + teno6(fm, CT);
+}
+
+constexpr int EXT_MAX = 640;     // tile extended by 3 + 3 cells along one axis
+constexpr int FACE_MAX = 320;    // faces of a tile along one axis
+constexpr int STG = (EXT_MAX + BLK - 1) / BLK;
+constexpr int FPT = (FACE_MAX + BLK - 1) / BLK;
+
+__device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
+  return ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
+}
+
+// Sources plus convective flux differences of every active direction, per
+// cell, into part[nv][N].  Per direction the tile and a 3-cell halo along
+// that direction are staged in LDS (velocity, pressure, sound speed, sensor
+// flag, then one conserved variable at a time); every face is evaluated
+// once: its hybrid decision and Lax-Friedrichs speed once for all
+// variables, then its flux for each variable.
+template <int NS>
+__global__ __launch_bounds__(BLK, 3) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                              int nmem, CallArgs A, const double* __restrict__ Ub,
+                                              const double* __restrict__ auxb, const double* __restrict__ srcb,
+                                              const unsigned char* __restrict__ flagb, double* __restrict__ partb,
+                                              double psi_c, double CT) {
+  constexpr int NV = NS + 4, NAUX = 7 + NS;
+  __shared__ double s_ud[EXT_MAX], s_p[EXT_MAX], s_c[EXT_MAX], s_U[2][EXT_MAX], s_F[2][FACE_MAX];
+  __shared__ unsigned char s_fl[EXT_MAX];
+  const int m = find_member_tiled(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const int t = threadIdx.x;
+  int o[3];
+  tile_origin(G, blockIdx.x - G.tblock_begin, o);
+  const int T0 = G.tdim[0], T1 = G.tdim[1], T2 = G.tdim[2];
+  const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
+  const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+  const bool valid = gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
+  const long long N = G.N;
+  const double* U = Ub + NV * G.off;
+  const double* aux = auxb + NAUX * G.off;
+  const unsigned char* flag = flagb + G.off;
+  const long long q = valid ? lin(G, gc) : 0;
+  double acc[NV];
+  const double* src = srcb + (NS + 1) * G.off;
 #pragma unroll
-    for (int o = 0; o < 7; ++o) {
-      uv[o] = U[v * N + qo[o]];
-      f[o] = node_flux<NS>(v, d, uv[o], ud[o], pp[o]);
-    }
-    double F[2];
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (valid) {
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const bool te = side ? tR : tL;
-      const double* fs = f + side;
-      if (!te) {
-        // divided (not multiplied by 1/60) so that the rounding cannot be
-        // fused into the face difference below: equal faces cancel exactly
-        F[side] = (fs[0] - 8.0 * fs[1] + 37.0 * fs[2] + 37.0 * fs[3] - 8.0 * fs[4] + fs[5]) / 60.0;
-      } else {
-        const double al = side ? aR : aL;
-        const double* us = uv + side;
-        double fp[6], fm[6];
+    for (int v = 0; v < NS; ++v) acc[v] = src[v * N + q];
+    acc[NS + 3] = src[NS * N + q];
+  }
+  const unsigned flags = A.flags;
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    int B[3] = {T0, T1, T2};
+    B[d] += 6;
+    const int E = B[0] * B[1] * B[2];
+    int FB[3] = {T0, T1, T2};
+    FB[d] += 1;
+    const int F = FB[0] * FB[1] * FB[2];
+    const int bstride = d == 0 ? 1 : (d == 1 ? B[0] : B[0] * B[1]);
+    // stage per-cell fields of the extended box; keep the global indices
+    long long qe[STG];
 #pragma unroll
-        for (int mm = 0; mm < 6; ++mm) {
-          fp[mm] = 0.5 * (fs[mm] + al * us[mm]);
-          fm[5 - mm] = 0.5 * (fs[mm] - al * us[mm]);
-        }
-        F[side] = teno6(fp, CT) + teno6(fm, CT);
+    for (int k = 0; k < STG; ++k) {
+      const int e = t + k * BLK;
+      qe[k] = 0;
+      if (e < E) {
+        const int b[3] = {e % B[0], (e / B[0]) % B[1], e / (B[0] * B[1])};
+        int g[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a] = wrapi(o[a] + b[a] - (a == d ? 3 : 0), G.n[a]);
+        qe[k] = lin(G, g);
+        s_ud[e] = aux[(4 + d) * N + qe[k]];
+        s_p[e] = aux[qe[k]];
+        s_c[e] = aux[N + qe[k]];
+        s_fl[e] = flag[qe[k]];
       }
     }
-    acc[v] -= xi * (F[1] - F[0]);
+    __syncthreads();
+    // this thread's faces: hybrid decision and LF speed
+    int fe0[FPT];
+    bool fte[FPT];
+    double fal[FPT];
+#pragma unroll
+    for (int k = 0; k < FPT; ++k) {
+      const int f = t + k * BLK;
+      fe0[k] = -1;
+      fte[k] = false;
+      fal[k] = 0.0;
+      if (f < F) {
+        const int fb[3] = {f % FB[0], (f / FB[0]) % FB[1], f / (FB[0] * FB[1])};
+        // stencil positions j-3..j+2 of the tile = box positions j..j+5 along d
+        fe0[k] = fb[0] + B[0] * (fb[1] + B[1] * fb[2]);
+        const int e0 = fe0[k];
+        bool te;
+        if (flags & HTR_FORCE_TENO) te = true;
+        else if (flags & HTR_FORCE_CENTRAL) te = false;
+        else {
+          int any = 0;
+#pragma unroll
+          for (int mm = 0; mm < 6; ++mm) any |= s_fl[e0 + mm * bstride];
+          const double pa = s_p[e0 + 2 * bstride], pb = s_p[e0 + 3 * bstride];
+          const double psi = fabs(pb - pa) / fmin(pa, pb);
+          te = any != 0 || psi > psi_c;
+        }
+        fte[k] = te;
+        if (te) {
+          double al = fabs(s_ud[e0]) + s_c[e0];
+#pragma unroll
+          for (int mm = 1; mm < 6; ++mm) al = fmax(al, fabs(s_ud[e0 + mm * bstride]) + s_c[e0 + mm * bstride]);
+          fal[k] = al;
+        }
+      }
+    }
+    int lf[3] = {l[0], l[1], l[2]};
+    const int fL = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
+    lf[d] += 1;
+    const int fR = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
+    const double xi = valid ? G.xin[d][gc[d]] : 0.0;
+    // software pipeline: the next variable's staging loads are in flight
+    // while the current variable's faces are evaluated (double-buffered LDS)
+    double nxt[STG];
+#pragma unroll
+    for (int k = 0; k < STG; ++k) nxt[k] = (t + k * BLK < E) ? U[qe[k]] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double* sU = s_U[v & 1];
+      double* sF = s_F[v & 1];
+#pragma unroll
+      for (int k = 0; k < STG; ++k) {
+        const int e = t + k * BLK;
+        if (e < E) sU[e] = nxt[k];
+      }
+      if (v + 1 < NV) {
+#pragma unroll
+        for (int k = 0; k < STG; ++k) nxt[k] = (t + k * BLK < E) ? U[(v + 1) * N + qe[k]] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        if (fe0[k] < 0) continue;
+        const int e0 = fe0[k];
+        double f6[6], u6[6];
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) {
+          const int e = e0 + mm * bstride;
+          u6[mm] = sU[e];
+          f6[mm] = node_flux<NS>(v, d, u6[mm], s_ud[e], s_p[e]);
+        }
+        double Fh;
+        if (!fte[k]) {
+          // the face value goes through LDS before it is differenced, so its
+          // last rounding cannot be fused into the difference
+          Fh = (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
+        } else {
+          Fh = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4], u6[5],
+                         fal[k], CT);
+        }
+        sF[t + k * BLK] = Fh;
+      }
+      __syncthreads();
+      if (valid) acc[v] -= xi * (sF[fR] - sF[fL]);
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    double* part = partb + NV * G.off;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) part[v * N + q] = acc[v];
   }
 }
 
-// Diffusive flux at the face between nodes qA and qB (B = A + 1 along d),
-// in the sign with which it enters the right-hand side, written to Fd[NV].
+// Diffusive flux at the face between nodes qA and qB = A + e_d, in the sign
+// with which it enters the right-hand side.  Tangential velocity derivatives
+// at the face are the mean of the nodal central differences (grad).
 template <int NS>
-__device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, const Member& G, int d,
-                                          const int cA[3], long long qA, long long qB, long long N,
-                                          const double* __restrict__ U, const double* __restrict__ T,
-                                          const double* __restrict__ aux, double* Fd) {
-  const double xf = G.xif[d][cA[d]];
-  int cB[3] = {cA[0], cA[1], cA[2]};
-  cB[d] = wrapi(cA[d] + 1, G.n[d]);
-  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+__device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, const Member& G, int d, int cAd,
+                                          long long qA, long long qB, long long N, const double* __restrict__ U,
+                                          const double* __restrict__ T, const double* __restrict__ aux,
+                                          const double* __restrict__ grad, double* Fd) {
+  const double xf = G.xif[d][cAd];
   double uA[3], uB[3];
 #pragma unroll
   for (int mm = 0; mm < 3; ++mm) {
@@ -121,23 +251,11 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int mm = 0; mm < 3; ++mm) g[a][mm] = 0.0;
-#pragma unroll
-  for (int mm = 0; mm < 3; ++mm) g[d][mm] = xf * (uB[mm] - uA[mm]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (a == d || !G.act[a]) continue;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int* cc = side ? cB : cA;
-      const long long qc = side ? qB : qA;
-      const long long qp = qc + (long long)(wrapi(cc[a] + 1, G.n[a]) - cc[a]) * strides[a];
-      const long long qm = qc + (long long)(wrapi(cc[a] - 1, G.n[a]) - cc[a]) * strides[a];
-      const double xa = 0.5 * G.xin[a][cc[a]];
-#pragma unroll
-      for (int mm = 0; mm < 3; ++mm) g[a][mm] += 0.5 * (xa * (aux[(4 + mm) * N + qp] - aux[(4 + mm) * N + qm]));
+    for (int mm = 0; mm < 3; ++mm) {
+      if (a == d) g[a][mm] = xf * (uB[mm] - uA[mm]);
+      else if (G.act[a]) g[a][mm] = 0.5 * (grad[(3 * a + mm) * N + qA] + grad[(3 * a + mm) * N + qB]);
+      else g[a][mm] = 0.0;
     }
-  }
   const double muf = 0.5 * (aux[2 * N + qA] + aux[2 * N + qB]);
   const double lamf = 0.5 * (aux[3 * N + qA] + aux[3 * N + qB]);
   const double divu = g[0][0] + g[1][1] + g[2][2];
@@ -158,8 +276,8 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
     nB += b * M->iW[s];
   }
   const double rhof = 0.5 * (rA + rB);
-  const double Wf = 0.5 * (rA / nA + rB / nB);
   const double inA = 1.0 / nA, inB = 1.0 / nB, irA = 1.0 / rA, irB = 1.0 / rB;
+  const double iWf = 1.0 / (0.5 * (rA * inA + rB * inB));
   double term[NS];
   double corr = 0.0;
 #pragma unroll
@@ -175,17 +293,17 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
       XB = b * M->iW[s] * inB;
     }
     const double dX = xf * (XB - XA);
-    term[s] = rhof * Df * (M->W[s] / Wf) * dX;
+    term[s] = rhof * Df * (M->W[s] * iWf) * dX;
     corr += term[s];
   }
-  const double TA = T[qA], TB = T[qB];
+  const double TA = T[qA], TB = T[qB], iTA = 1.0 / TA, iTB = 1.0 / TB;
   double qn = -lamf * xf * (TB - TA);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const double a = U[s * N + qA], b = U[s * N + qB];
     const double Yf = 0.5 * (a * irA + b * irB);
     const double J = -term[s] + Yf * corr;
-    const double hf = 0.5 * (M->RW[s] * TA * hRTs(M, s, TA) + M->RW[s] * TB * hRTs(M, s, TB));
+    const double hf = 0.5 * (M->RW[s] * TA * hRTi(M, s, TA, iTA) + M->RW[s] * TB * hRTi(M, s, TB, iTB));
     qn += J * hf;
     Fd[s] = -J;
   }
@@ -198,48 +316,73 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
   Fd[NS + 3] = work - qn;
 }
 
+// Diffusive flux differences (each face once, exchanged through LDS) added
+// to part, then the SSP-RK3 stage combination (or dU/dt when rhs_only).
 template <int NS>
-__global__ __launch_bounds__(BLK) void k_sweep(const MechTables* __restrict__ M, const Member* __restrict__ mem,
-                                               int nmem, CallArgs A, const double* __restrict__ Ub,
-                                               const double* __restrict__ Unb, const double* __restrict__ Tb,
-                                               const double* __restrict__ auxb, const double* __restrict__ srcb,
-                                               const unsigned char* __restrict__ flagb, double* __restrict__ outb,
-                                               double ca, double cb, int rhs_only, double psi_c, double CT) {
+__global__ __launch_bounds__(BLK, 3) void k_diff(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                              int nmem, CallArgs A, const double* __restrict__ Ub,
+                                              const double* Unb, const double* __restrict__ Tb,
+                                              const double* __restrict__ auxb, const double* __restrict__ gradb,
+                                              const double* __restrict__ partb, double* outb, double ca, double cb,
+                                              int rhs_only) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
-  const int m = find_member(mem, nmem, blockIdx.x);
+  __shared__ double s_Fd[NV][FACE_MAX];
+  const int m = find_member_tiled(mem, nmem, blockIdx.x);
   const Member& G = mem[m];
-  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
-  if (q >= G.N) return;
+  const int t = threadIdx.x;
+  int o[3];
+  tile_origin(G, blockIdx.x - G.tblock_begin, o);
+  const int T0 = G.tdim[0], T1 = G.tdim[1], T2 = G.tdim[2];
+  const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
+  const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+  const bool valid = gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
   const long long N = G.N;
   const double* U = Ub + NV * G.off;
   const double* T = Tb + G.off;
   const double* aux = auxb + NAUX * G.off;
-  const double* src = srcb + (NS + 1) * G.off;
-  const unsigned char* flag = flagb + G.off;
-  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
-  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  const double* grad = gradb + 9 * G.off;
+  const long long q = valid ? lin(G, gc) : 0;
   double acc[NV];
+  const double* part = partb + NV * G.off;
 #pragma unroll
-  for (int v = 0; v < NS; ++v) acc[v] = src[v * N + q];
-  acc[NS] = acc[NS + 1] = acc[NS + 2] = 0.0;
-  acc[NS + 3] = src[NS * N + q];
-  const unsigned flags = A.flags;
-  for (int d = 0; d < 3; ++d) {
-    if (!G.act[d]) continue;
-    conv_dir<NS>(G, d, c, q, N, U, aux, flag, flags, psi_c, CT, acc);
-    if (!(flags & HTR_VISC_OFF)) {
-      const double xi = G.xin[d][c[d]];
-      int cm[3] = {c[0], c[1], c[2]};
-      cm[d] = wrapi(c[d] - 1, G.n[d]);
-      const long long qm = q + (long long)(cm[d] - c[d]) * strides[d];
-      const long long qp = q + (long long)(wrapi(c[d] + 1, G.n[d]) - c[d]) * strides[d];
-      double FL[NV], FR[NV];
-      diff_face<NS>(M, G, d, cm, qm, q, N, U, T, aux, FL);
-      diff_face<NS>(M, G, d, c, q, qp, N, U, T, aux, FR);
+  for (int v = 0; v < NV; ++v) acc[v] = valid ? part[v * N + q] : 0.0;
+  if (!(A.flags & HTR_VISC_OFF)) {
+    for (int d = 0; d < 3; ++d) {
+      if (!G.act[d]) continue;
+      int FB[3] = {T0, T1, T2};
+      FB[d] += 1;
+      const int F = FB[0] * FB[1] * FB[2];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += xi * (FR[v] - FL[v]);
+      for (int k = 0; k < FPT; ++k) {
+        const int f = t + k * BLK;
+        if (f >= F) continue;
+        const int fb[3] = {f % FB[0], (f / FB[0]) % FB[1], f / (FB[0] * FB[1])};
+        int gA[3], gB[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int c0 = o[a] + fb[a] - (a == d ? 1 : 0);
+          gA[a] = wrapi(c0, G.n[a]);
+          gB[a] = a == d ? wrapi(c0 + 1, G.n[a]) : gA[a];
+        }
+        double Fd[NV];
+        diff_face<NS>(M, G, d, gA[d], lin(G, gA), lin(G, gB), N, U, T, aux, grad, Fd);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s_Fd[v][f] = Fd[v];
+      }
+      __syncthreads();
+      if (valid) {
+        int lf[3] = {l[0], l[1], l[2]};
+        const int fL = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
+        lf[d] += 1;
+        const int fR = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
+        const double xi = G.xin[d][gc[d]];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += xi * (s_Fd[v][fR] - s_Fd[v][fL]);
+      }
+      __syncthreads();
     }
   }
+  if (!valid) return;
   double* out = outb + NV * G.off;
   if (rhs_only) {
 #pragma unroll
@@ -256,20 +399,25 @@ __global__ __launch_bounds__(BLK) void k_sweep(const MechTables* __restrict__ M,
 }
 
 template <int NS>
-static hipError_t sweep_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+static hipError_t sweep_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
                           const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                          const unsigned char* flag, double* out, double ca, double cb, int rhs_only, double psi_c,
-                          double CT, hipStream_t s) {
-  hipLaunchKernelGGL(k_sweep<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, Un, T, aux, src, flag, out,
-                     ca, cb, rhs_only, psi_c, CT);
+                          const unsigned char* flag, const double* grad, double* part, double* out, double ca,
+                          double cb, int rhs_only, double psi_c, double CT, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv<NS>, dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part, psi_c,
+                     CT);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diff<NS>, dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, Un, T, aux, grad, part, out,
+                     ca, cb, rhs_only);
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
                         const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                        const unsigned char* flag, double* out, double ca, double cb, int rhs_only, double psi_c,
-                        double CT, hipStream_t s) {
-#define C_(NS) sweep_t<NS>(M, mem, nmem, nblocks, a, U, Un, T, aux, src, flag, out, ca, cb, rhs_only, psi_c, CT, s)
+                        const unsigned char* flag, const double* grad, double* part, double* out, double ca,
+                        double cb, int rhs_only, double psi_c, double CT, hipStream_t s) {
+#define C_(NS) sweep_t<NS>(M, mem, nmem, ntblocks, a, U, Un, T, aux, src, flag, grad, part, out, ca, cb, rhs_only, \
+                           psi_c, CT, s)
   switch (ns) {
     case 1: return C_(1); case 2: return C_(2); case 3: return C_(3);
     case 4: return C_(4); case 5: return C_(5); case 6: return C_(6);
