@@ -62,8 +62,8 @@ __device__ __forceinline__ double om11a(double x, double Ts, double iT, double i
 }
 
 // ------------------------------------------------------------ convective
-template <int NS>
-__device__ __forceinline__ void adj_conv(const Member& G, int d, const int c[3], long long q, long long N,
+template <int NS, int d>
+__device__ __forceinline__ void adj_conv(const Member& G, const int c[3], long long q, long long N,
                                          const double* __restrict__ U, const double* __restrict__ aux,
                                          const unsigned char* __restrict__ flag, const double* __restrict__ lam,
                                          double s, unsigned flags, double psi_c, double CT, double* ubar,
@@ -193,8 +193,8 @@ __device__ __forceinline__ void adj_conv(const Member& G, int d, const int c[3],
 // ------------------------------------------------------------- diffusive
 // Face (A, B = A + e_d): adds the cotangent contributions to node A
 // (side = 0) or node B (side = 1).
-template <int NS>
-__device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, const Member& G, int d,
+template <int NS, int d>
+__device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, const Member& G,
                                               const int cA[3], long long qA, long long qB, long long N,
                                               const double* __restrict__ U, const double* __restrict__ T,
                                               const double* __restrict__ aux, const double* __restrict__ lam,
@@ -226,11 +226,11 @@ __device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, 
     if (a == d || !G.act[a]) continue;
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-      const int* cc = sd ? cB : cA;
+      const int cca = sd ? cB[a] : cA[a];
       const long long qc = sd ? qB : qA;
-      const long long qp = qc + (long long)(wrapi(cc[a] + 1, G.n[a]) - cc[a]) * strides[a];
-      const long long qm = qc + (long long)(wrapi(cc[a] - 1, G.n[a]) - cc[a]) * strides[a];
-      const double xa = 0.5 * G.xin[a][cc[a]];
+      const long long qp = qc + (long long)(wrapi(cca + 1, G.n[a]) - cca) * strides[a];
+      const long long qm = qc + (long long)(wrapi(cca - 1, G.n[a]) - cca) * strides[a];
+      const double xa = 0.5 * G.xin[a][cca];
 #pragma unroll
       for (int mm = 0; mm < 3; ++mm) g[a][mm] += 0.5 * (xa * (aux[(4 + mm) * N + qp] - aux[(4 + mm) * N + qm]));
     }
@@ -257,16 +257,15 @@ __device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, 
   const double rhof = 0.5 * (rA + rB);
   const double Wf = 0.5 * (rA / nA + rB / nB);
   const double TA = T[qA], TB = T[qB];
-  double term[NS], dX[NS], Df[NS], Yf[NS], J[NS];
+  // pass 1: corr = sum_k term_k (per-species values are recomputed from
+  // cached loads in every pass instead of being held in registers)
   double corr = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double a = U[k * N + qA], b = U[k * N + qB];
-    Df[k] = 0.5 * (aux[(7 + k) * N + qA] + aux[(7 + k) * N + qB]);
-    dX[k] = xf * (b * M->iW[k] / nB - a * M->iW[k] / nA);
-    term[k] = rhof * Df[k] * (M->W[k] / Wf) * dX[k];
-    corr += term[k];
-    Yf[k] = 0.5 * (a / rA + b / rB);
+    const double Df = 0.5 * (aux[(7 + k) * N + qA] + aux[(7 + k) * N + qB]);
+    const double dX = xf * (b * M->iW[k] / nB - a * M->iW[k] / nA);
+    corr += rhof * Df * (M->W[k] / Wf) * dX;
   }
   // ---- reverse
   const double qnb = -Gv[NS + 3];
@@ -275,30 +274,50 @@ __device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, 
   for (int mm = 0; mm < 3; ++mm) taub[mm] = Gv[NS + mm] + Gv[NS + 3] * uf[mm];
   const double lamfb = -qnb * xf * (TB - TA);
   double TAb = qnb * lamf * xf, TBb = -qnb * lamf * xf;
+  // pass 2: species flux cotangents
   double Jb[NS];
+  double corrb = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    J[k] = -term[k] + Yf[k] * corr;
+    const double a = U[k * N + qA], b = U[k * N + qB];
+    const double Df = 0.5 * (aux[(7 + k) * N + qA] + aux[(7 + k) * N + qB]);
+    const double dX = xf * (b * M->iW[k] / nB - a * M->iW[k] / nA);
+    const double term = rhof * Df * (M->W[k] / Wf) * dX;
+    const double Yf = 0.5 * (a / rA + b / rB);
+    const double J = -term + Yf * corr;
     const double hA = M->RW[k] * TA * hRTs(M, k, TA), hB = M->RW[k] * TB * hRTs(M, k, TB);
-    const double hfb = qnb * J[k];
+    const double hfb = qnb * J;
     TAb += hfb * 0.5 * M->RW[k] * cpRa(M, k, TA);
     TBb += hfb * 0.5 * M->RW[k] * cpRa(M, k, TB);
     Jb[k] = -Gv[k] + qnb * 0.5 * (hA + hB);
+    corrb += Jb[k] * Yf;
   }
-  double corrb = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) corrb += Jb[k] * Yf[k];
-  double rhofb = 0.0, Wfb = 0.0;
-  double dXb[NS], Yfb[NS], Dfb[NS];
+  // pass 3: back to the node's partial densities and diffusivities
+  const double sgn = side ? 1.0 : -1.0;          // d(dX)/dX_B = +xf, d(dX)/dX_A = -xf
+  const double rn = side ? rB : rA, nn = side ? nB : nA;
+  const long long qn = side ? qB : qA;
+  double rhofb = 0.0, Wfb = 0.0, nbar = 0.0, rbar = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
+    const double a = U[k * N + qA], b = U[k * N + qB], an = U[k * N + qn];
+    const double Df = 0.5 * (aux[(7 + k) * N + qA] + aux[(7 + k) * N + qB]);
+    const double dX = xf * (b * M->iW[k] / nB - a * M->iW[k] / nA);
+    const double term = rhof * Df * (M->W[k] / Wf) * dX;
     const double termb = -Jb[k] + corrb;
-    Yfb[k] = Jb[k] * corr;
-    rhofb += termb * Df[k] * (M->W[k] / Wf) * dX[k];
-    Dfb[k] = termb * rhof * (M->W[k] / Wf) * dX[k];
-    Wfb -= termb * term[k] / Wf;
-    dXb[k] = termb * rhof * Df[k] * M->W[k] / Wf;
+    const double Yfb = Jb[k] * corr;
+    rhofb += termb * Df * (M->W[k] / Wf) * dX;
+    Wfb -= termb * term / Wf;
+    pb[PB_D + k] += 0.5 * termb * rhof * (M->W[k] / Wf) * dX;
+    const double Xb = sgn * termb * rhof * Df * M->W[k] / Wf * xf;
+    const double Xn = an * M->iW[k] / nn;
+    nbar -= Xb * Xn / nn;
+    rbar -= 0.5 * Yfb * an / (rn * rn);
+    ubar[k] += Xb * M->iW[k] / nn + 0.5 * Yfb / rn;
   }
+  rbar += 0.5 * Wfb / nn + 0.5 * rhofb;
+  nbar += -0.5 * Wfb * rn / (nn * nn);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) ubar[k] += rbar + nbar * M->iW[k];
   double mufb = -(2.0 / 3.0) * taub[d] * divu;
 #pragma unroll
   for (int mm = 0; mm < 3; ++mm) mufb += taub[mm] * (g[d][mm] + g[mm][d]);
@@ -307,25 +326,6 @@ __device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, 
 #pragma unroll
   for (int mm = 0; mm < 3; ++mm) gdb[mm] = muf * taub[mm];
   gdb[d] = (4.0 / 3.0) * muf * taub[d];
-  // node-side contributions
-  const double sgn = side ? 1.0 : -1.0;          // d(dX)/dX_B = +xf, d(dX)/dX_A = -xf
-  const double rn = side ? rB : rA, nn = side ? nB : nA;
-  const long long qn = side ? qB : qA;
-  double rbar = 0.5 * Wfb / nn + 0.5 * rhofb;
-  double nbar = -0.5 * Wfb * rn / (nn * nn);
-  double Xn[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const double a = U[k * N + qn];
-    Xn[k] = a * M->iW[k] / nn;
-    const double Xb = sgn * dXb[k] * xf;
-    nbar -= Xb * Xn[k] / nn;
-    rbar -= 0.5 * Yfb[k] * a / (rn * rn);
-    ubar[k] += Xb * M->iW[k] / nn + 0.5 * Yfb[k] / rn;
-    pb[PB_D + k] += 0.5 * Dfb[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) ubar[k] += rbar + nbar * M->iW[k];
   pb[PB_T] += side ? TBb : TAb;
   pb[PB_MU] += 0.5 * mufb;
   pb[PB_LAM] += 0.5 * lamfb;
@@ -335,8 +335,8 @@ __device__ __forceinline__ void adj_diff_face(const MechTables* __restrict__ M, 
 
 // Tangential-neighbour contributions: node q is u(A +- e_t) or u(B +- e_t)
 // of the d-face (A, A + e_d).
-template <int NS>
-__device__ __forceinline__ void adj_diff_tangential(const Member& G, int d, int t, const int c[3], long long q,
+template <int NS, int d, int t>
+__device__ __forceinline__ void adj_diff_tangential(const Member& G, const int c[3], long long q,
                                                     long long N, const double* __restrict__ aux,
                                                     const double* __restrict__ lam, double s, double* pb) {
   constexpr int NV = NS + 4;
@@ -370,7 +370,28 @@ __device__ __forceinline__ void adj_diff_tangential(const Member& G, int d, int 
   (void)NV;
 }
 
-template <int NS>
+// All diffusive contributions of direction d to a node: the two faces of
+// which it is a node, and the faces of which it is a tangential neighbour.
+template <int NS, int d>
+__device__ __forceinline__ void adj_diff_dir(const MechTables* __restrict__ M, const Member& G, const int c[3],
+                                             long long q, long long N, const double* __restrict__ U,
+                                             const double* __restrict__ T, const double* __restrict__ aux,
+                                             const double* __restrict__ lam, double s, double* ubar, double* pb) {
+  const long long stride = d == 0 ? 1 : (d == 1 ? (long long)G.n[0] : (long long)G.n[0] * G.n[1]);
+  int cm[3] = {c[0], c[1], c[2]};
+  cm[d] = wrapi(c[d] - 1, G.n[d]);
+  const long long qm = q + (long long)(cm[d] - c[d]) * stride;
+  const long long qp = q + (long long)(wrapi(c[d] + 1, G.n[d]) - c[d]) * stride;
+  adj_diff_face<NS, d>(M, G, cm, qm, q, N, U, T, aux, lam, s, 1, ubar, pb);
+  adj_diff_face<NS, d>(M, G, c, q, qp, N, U, T, aux, lam, s, 0, ubar, pb);
+  constexpr int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  if (G.act[t1]) adj_diff_tangential<NS, d, t1>(G, c, q, N, aux, lam, s, pb);
+  if (G.act[t2]) adj_diff_tangential<NS, d, t2>(G, c, q, N, aux, lam, s, pb);
+}
+
+// PART 0: convective faces (writes the cotangents); PART 1: diffusive faces
+// (adds to them).  Two kernels keep each one's register footprint small.
+template <int NS, int PART>
 __global__ __launch_bounds__(BLK) void k_adj_sweep(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                                    int nmem, CallArgs A, const double* __restrict__ Ub,
                                                    const double* __restrict__ Tb, const double* __restrict__ auxb,
@@ -392,27 +413,22 @@ __global__ __launch_bounds__(BLK) void k_adj_sweep(const MechTables* __restrict_
   const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
   const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
   double ubar[NV], pb[NPB];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) ubar[v] = 0.0;
-#pragma unroll
-  for (int k = 0; k < NPB; ++k) pb[k] = 0.0;
-  const unsigned flags = A.flags;
-  for (int d = 0; d < 3; ++d) {
-    if (!G.act[d]) continue;
-    adj_conv<NS>(G, d, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
-    if (!(flags & HTR_VISC_OFF)) {
-      int cm[3] = {c[0], c[1], c[2]};
-      cm[d] = wrapi(c[d] - 1, G.n[d]);
-      const long long qm = q + (long long)(cm[d] - c[d]) * strides[d];
-      const long long qp = q + (long long)(wrapi(c[d] + 1, G.n[d]) - c[d]) * strides[d];
-      adj_diff_face<NS>(M, G, d, cm, qm, q, N, U, T, aux, lam, s, 1, ubar, pb);
-      adj_diff_face<NS>(M, G, d, c, q, qp, N, U, T, aux, lam, s, 0, ubar, pb);
-      for (int t = 0; t < 3; ++t)
-        if (t != d && G.act[t]) adj_diff_tangential<NS>(G, d, t, c, q, N, aux, lam, s, pb);
-    }
-  }
   double* ubd = ubdb + NV * G.off;
   double* pbo = pbb + NPB * G.off;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ubar[v] = PART ? ubd[v * N + q] : 0.0;
+#pragma unroll
+  for (int k = 0; k < NPB; ++k) pb[k] = PART ? pbo[k * N + q] : 0.0;
+  const unsigned flags = A.flags;
+  if (PART == 0) {
+    if (G.act[0]) adj_conv<NS, 0>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
+    if (G.act[1]) adj_conv<NS, 1>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
+    if (G.act[2]) adj_conv<NS, 2>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
+  } else if (!(flags & HTR_VISC_OFF)) {
+    if (G.act[0]) adj_diff_dir<NS, 0>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
+    if (G.act[1]) adj_diff_dir<NS, 1>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
+    if (G.act[2]) adj_diff_dir<NS, 2>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) ubd[v * N + q] = ubar[v];
 #pragma unroll
@@ -830,10 +846,16 @@ static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nb
                         const double* U, const double* T, const double* aux, const unsigned char* flag,
                         const double* lam, double s, double h, double* ubd, double* pbv, double* out,
                         double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_sweep<NS>, dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam, s, ubd,
-                     pbv, psi_c, CT);
+  hipLaunchKernelGGL((k_adj_sweep<NS, 0>), dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam, s,
+                     ubd, pbv, psi_c, CT);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (!(a.flags & HTR_VISC_OFF)) {
+    hipLaunchKernelGGL((k_adj_sweep<NS, 1>), dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam,
+                       s, ubd, pbv, psi_c, CT);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_adj_point<NS>, dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, pbv, ubd, lam, s, h, out,
                      thpart, nth);
   return hipGetLastError();
