@@ -14,10 +14,13 @@ Prints one JSON line.  `value` = cells x 3 stages x steps / time.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -42,18 +45,76 @@ def point_flops_per_cell(ns, nr, laser_on, newton_iters=3):
     return newton + thermo + transport + chem + laser + misc + EXP_WEIGHT * (trans_exp + chem_exp + laser_exp)
 
 
-def sweep_bytes_per_cell(ns):
-    """Algorithmic HBM bytes of the fused sweep per cell and stage: read U,
-    T, the per-cell fields (p, c, mu, lambda, u, v, w, D_s), the sources
-    (wdot_s, q_L), the sensor byte and (stages 2-3) U^n; write the stage."""
+def conv_bytes_per_cell(ns):
+    """Algorithmic HBM bytes of the convective sweep per cell and stage:
+    read U, the per-cell p, c, u, v, w, the sensor byte and the sources
+    (wdot_s, q_L); write the partial right-hand side."""
     nv = ns + 4
-    reads = 8 * (nv + 1 + (7 + ns) + (ns + 1)) + 1 + 8 * nv * 2.0 / 3.0
-    return reads + 8 * nv
+    return 8 * nv + 8 * 5 + 1 + 8 * (ns + 1) + 8 * nv
+
+
+def diff_bytes_per_cell(ns):
+    """Algorithmic HBM bytes of the diffusive sweep with the stage update per
+    cell and stage: read U, u, v, w, mu, lambda, D_s, the nine velocity
+    gradients, T, the partial right-hand side and (stages 2-3, so 2/3 on
+    average) U^n; write the new stage."""
+    nv = ns + 4
+    return 8 * nv + 8 * (5 + ns) + 8 * 9 + 8 + 8 * nv + 8 * nv * 2.0 / 3.0 + 8 * nv
 
 
 def point_bytes_per_cell(ns):
+    """Read U and T; write T, the per-cell fields and the sources."""
     nv = ns + 4
     return 8 * (nv + 1) + 8 * (1 + (7 + ns) + (ns + 1))
+
+
+CSRC = os.path.join(ROOT, "paper_2202_02319_amd", "csrc")
+KERNEL_SOURCES = {
+    "k_point": ("htr_point.hip", "htr_dev.h", "htr_flux.h"),
+    "k_conv": ("htr_sweep.hip", "htr_dev.h", "htr_flux.h"),
+    "k_diff": ("htr_sweep.hip", "htr_dev.h", "htr_flux.h"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_tgv128.md")
+
+
+def kernel_source_hash(kernel):
+    """Short SHA-256 of the source files a kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    same counter's reading on a plain copy of known size) from the committed
+    counter summary; None if there is none for this kernel and workload or
+    if the kernel's sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("workload") == workload:
+                if kv.get("sha") != kernel_source_hash(kernel):
+                    return None
+                return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
+def calibration_copy(nbytes=1 << 30):
+    """A plain device copy of known size (read nbytes, write nbytes) that a
+    counter run uses to scale FETCH_SIZE and WRITE_SIZE to bytes."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def cpu_baseline(case, seconds_target=15.0):
@@ -92,16 +153,18 @@ def cpu_baseline(case, seconds_target=15.0):
                       f"slab of the workload, {el:.2f} s"}
 
 
-def ensemble_measure(steps, warm=1):
-    """The 64-member ensemble (N^3 members, N uniform on {32, 40, ..., 96},
-    perturbed deposition energy, kernel centre and ln A): `steps` RK3 steps
-    of all members as one captured HIP-graph launch (one launch per kernel
-    over all members' tiles), against the same steps driven member by member
-    (one htr_rk3_step per member and step, one stream)."""
+def ensemble_measure(steps, warm=1, sizes=None):
+    """The 64-member ensemble (N^3 members, N uniform on {32, 40, ..., 96}
+    unless `sizes` gives the N of each member; perturbed deposition energy,
+    kernel centre and ln A): `steps` RK3 steps of all members as one captured
+    HIP-graph launch (one launch per kernel over all members' tiles), against
+    the same steps driven member by member (one htr_rk3_step per member and
+    step, one stream)."""
     import torch
     import synth
     from paper_2202_02319_amd import htr
-    e = synth.ensemble_c4()
+    e = synth.ensemble_c4(sizes=sizes)
+    Ns = sorted({int(round(c.grid.N ** (1 / 3))) for c in e.members})
     ctx = htr.Context(e.mech, e.members[0].grid)
     b = htr.Batch.from_cases(ctx, e.members, e.dlnA)
     U, T = htr.batch_state_from_cases(b, e.members)
@@ -141,8 +204,8 @@ def ensemble_measure(steps, warm=1):
         htr.htr_check(g)
     t_m = e0.elapsed_time(e1) / 1e3
     cs = b.N * 3 * steps
-    return {"workload": f"64-member mixing-layer ensemble, N^3 members with N in {{32,...,96}}, {b.N} cells, "
-                        f"{steps} RK3 steps", "cells": b.N, "steps": steps,
+    return {"workload": f"{len(e.members)}-member mixing-layer ensemble, N^3 members with N in "
+                        f"{{{','.join(map(str, Ns))}}}, {b.N} cells, {steps} RK3 steps", "cells": b.N, "steps": steps,
             "batched_value": cs / t_b, "per_member_value": cs / t_m, "unit": "cell-stage updates/s",
             "batched_over_per_member": t_m / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
             "per_member_ms_per_step": 1e3 * t_m / steps}
@@ -195,6 +258,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (ensemble members or grid blocks "
@@ -247,17 +312,23 @@ def main():
     htr.htr_check(ctx)
     ns, nr = case.mech.ns, case.mech.nr
     avg = {k: (v[0] / max(v[1], 1), v[1]) for k, v in kt.items()}
-    dom = max(("point", "sweep"), key=lambda k: kt[k][0])
-    if dom == "sweep":
-        traffic_b = sweep_bytes_per_cell(ns) * N
-        ach = traffic_b / (avg["sweep"][0] / 1e3) / 1e9
-        roof = {"kernel": "k_sweep", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
-    else:
-        fl = point_flops_per_cell(ns, nr, laser is not None) * N
-        ach = fl / (avg["point"][0] / 1e3) / 1e12
-        roof = {"kernel": "k_point", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    # every main kernel against its own bound; the dominant one is reported
+    kern = {}
+    for k, name, bpc in (("conv", "k_conv", conv_bytes_per_cell(ns)), ("diff", "k_diff", diff_bytes_per_cell(ns))):
+        ach = bpc * N / (avg[k][0] / 1e3) / 1e9
+        kern[k] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell": round(bpc, 2)}
+    fl = point_flops_per_cell(ns, nr, laser is not None)
+    ach = fl * N / (avg["point"][0] / 1e3) / 1e12
+    kern["point"] = {"kernel": "k_point", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "flops_per_cell": fl}
+    dom = max(("point", "conv", "diff"), key=lambda k: kt[k][0])
+    roof = {k: v for k, v in kern[dom].items() if k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    tb = measured_traffic(kern[dom]["kernel"], args.workload)
+    roof["traffic"] = round(tb / (avg[dom][0] / 1e3) / 1e9, 1) if tb is not None else None
+    roof["traffic_bytes_per_launch"] = tb
+    roof["kernel_avg_ms"] = round(avg[dom][0], 4)
+    roof["all_kernels"] = kern
     roof["kernel_ms"] = {k: round(v[0], 4) for k, v in avg.items()}
     roof["step_ms_by_kernel"] = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
 
@@ -286,11 +357,18 @@ def main():
         del U, T, work
         torch.cuda.empty_cache()
         out["ensemble"] = ensemble_measure(args.ens_steps)
+        torch.cuda.empty_cache()
+        # small members (N = 12..24): each member alone fills a few CUs, so
+        # per-member launches are latency-bound and batching pays most
+        small = np.random.default_rng(12).choice(np.arange(12, 25, 4), size=64)
+        out["ensemble_small"] = ensemble_measure(args.ens_steps, sizes=small)
     if args.adj_steps > 0:
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_measure(args.adj_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    if args.calib_copy:
+        out["calibration_copy_bytes"] = calibration_copy()
     print(json.dumps(out), flush=True)
 
 

@@ -10,17 +10,22 @@
 // is that of the scheme with those switches fixed.  The Newton temperature is
 // differentiated through its implicit definition e(T, Y) = e.
 //
-// Two kernels per evaluation, after a forward per-cell pass on the state:
-//   k_adj_sweep  one thread per node: gathers from every face whose stencil
-//                contains the node (six convective faces per direction; two
-//                diffusive faces; four per tangential axis through the
-//                cross-derivatives) the cotangents of the node's conserved
-//                variables (direct) and of its per-cell fields
-//                (T, p, c, mu, lambda, u, D_s).  No atomics: deterministic.
-//   k_adj_point  one thread per cell: reverse of the per-cell physics
-//                (heat release, chemistry, Bird and Wilke transport, EOS,
-//                implicit Newton T), plus the laser's parameter derivatives;
-//                block partials of the parameter cotangent.
+// Three kernels per evaluation, after a forward per-cell pass on the state.
+// Each node gathers what it receives, so no atomics are used and the result
+// is deterministic:
+//   k_adj_conv_tiled  one 256-node tile per block: the six convective faces
+//                     per direction whose stencil contains the node, from
+//                     face decisions and TENO cut-off patterns evaluated once
+//                     per face in LDS; writes the cotangents of the node's
+//                     conserved variables (direct) and of its per-cell fields
+//                     (T, p, c, mu, lambda, u, D_s).
+//   k_adj_diff        one thread per node: the two diffusive faces per
+//                     direction and four per tangential axis through the
+//                     cross-derivatives; adds to those cotangents.
+//   k_adj_point       one thread per cell: reverse of the per-cell physics
+//                     (heat release, chemistry, Bird and Wilke transport,
+//                     EOS, implicit Newton T), plus the laser's parameter
+//                     derivatives; block partials of the parameter cotangent.
 
 #include <math.h>
 
@@ -59,135 +64,6 @@ __device__ __forceinline__ double om11a(double x, double Ts, double iT, double i
   const double e2 = 1.03587 * exp(-1.52996 * Ts), e3 = 1.76474 * exp(-3.89411 * Ts);
   *dT = -0.15610 * e0 * iT - (0.47635 * e1 + 1.52996 * e2 + 3.89411 * e3) * ieps;
   return e0 + e1 + e2 + e3;
-}
-
-// ------------------------------------------------------------ convective
-template <int NS, int d>
-__device__ __forceinline__ void adj_conv(const Member& G, const int c[3], long long q, long long N,
-                                         const double* __restrict__ U, const double* __restrict__ aux,
-                                         const unsigned char* __restrict__ flag, const double* __restrict__ lam,
-                                         double s, unsigned flags, double psi_c, double CT, double* ubar,
-                                         double* pb) {
-  constexpr int NV = NS + 4;
-  const int n = G.n[d];
-  const long long stride = d == 0 ? 1 : (d == 1 ? (long long)G.n[0] : (long long)G.n[0] * G.n[1]);
-  // window of 11 nodes: relative offsets -5..5
-  long long qo[11];
-  double ud[11], pp[11], cc[11];
-  int fl = 0;
-#pragma unroll
-  for (int o = 0; o < 11; ++o) {
-    qo[o] = q + (long long)(wrapi(c[d] + o - 5, n) - c[d]) * stride;
-    ud[o] = aux[(4 + d) * N + qo[o]];
-    pp[o] = aux[qo[o]];
-    cc[o] = aux[N + qo[o]];
-    fl |= (int)flag[qo[o]] << o;
-  }
-  double xi7[7];
-#pragma unroll
-  for (int o = 0; o < 7; ++o) xi7[o] = G.xin[d][wrapi(c[d] + o - 3, n)];
-  // faces k = 0..5: left node at offset k-3, stencil offsets k-5..k (window k..k+5)
-  bool te[6], use[6];
-  double al[6];
-  int am[6];
-  bool any = false;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    // a periodic axis shorter than the window revisits faces: count each once
-    use[k] = true;
-    const int fk = wrapi(c[d] + k - 3, n);
-#pragma unroll
-    for (int k2 = 0; k2 < k; ++k2)
-      if (wrapi(c[d] + k2 - 3, n) == fk) use[k] = false;
-    if (flags & HTR_FORCE_TENO) te[k] = true;
-    else if (flags & HTR_FORCE_CENTRAL) te[k] = false;
-    else {
-      const double pa = pp[k + 2], pbv = pp[k + 3];
-      const double psi = fabs(pbv - pa) / fmin(pa, pbv);
-      te[k] = ((fl >> k) & 0x3f) != 0 || psi > psi_c;
-    }
-    al[k] = 0.0;
-    am[k] = 0;
-    if (te[k]) {
-      double best = fabs(ud[k]) + cc[k];
-#pragma unroll
-      for (int mm = 1; mm < 6; ++mm) {
-        const double sp = fabs(ud[k + mm]) + cc[k + mm];
-        if (sp > best) { best = sp; am[k] = mm; }
-      }
-      al[k] = best;
-    }
-    any = any || (te[k] && use[k]);
-  }
-  const double C6[6] = {1.0 / 60.0, -8.0 / 60.0, 37.0 / 60.0, 37.0 / 60.0, -8.0 / 60.0, 1.0 / 60.0};
-  double abar[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double uv[11], f[11];
-    if (any) {
-#pragma unroll
-      for (int o = 0; o < 11; ++o) {
-        uv[o] = U[v * N + qo[o]];
-        f[o] = node_flux<NS>(v, d, uv[o], ud[o], pp[o]);
-      }
-    } else {
-      uv[5] = U[v * N + q];
-    }
-    double lv[7];
-#pragma unroll
-    for (int o = 0; o < 7; ++o) lv[o] = s * lam[v * N + qo[o + 2]];
-    double Fb = 0.0, Ub = 0.0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      if (!use[k]) continue;
-      const double g = -xi7[k] * lv[k] + xi7[k + 1] * lv[k + 1];
-      if (!te[k]) {
-#pragma unroll
-        for (int mm = 0; mm < 6; ++mm)
-          if (qo[k + mm] == q) Fb += g * C6[mm];
-      } else {
-        double fp[6], fm[6], cp[6], cm[6];
-#pragma unroll
-        for (int mm = 0; mm < 6; ++mm) {
-          fp[mm] = 0.5 * (f[k + mm] + al[k] * uv[k + mm]);
-          fm[5 - mm] = 0.5 * (f[k + mm] - al[k] * uv[k + mm]);
-        }
-        teno6_coeffs(fp, CT, cp);
-        teno6_coeffs(fm, CT, cm);
-        double da = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < 6; ++mm) {
-          const double dw = cp[mm] - cm[5 - mm];
-          da += dw * uv[k + mm];
-          if (qo[k + mm] == q) {
-            Fb += g * 0.5 * (cp[mm] + cm[5 - mm]);
-            Ub += g * 0.5 * al[k] * dw;
-          }
-        }
-        abar[k] += g * 0.5 * da;
-      }
-    }
-    // node flux F_v(U_v, u_d, p) at this node
-    const double un = ud[5];
-    Ub += Fb * un;
-    if (v == NS + 3) {
-      pb[PB_U + d] += Fb * (uv[5] + pp[5]);
-      pb[PB_P] += Fb * un;
-    } else {
-      pb[PB_U + d] += Fb * uv[5];
-      if (v == NS + d) pb[PB_P] += Fb;
-    }
-    ubar[v] += Ub;
-  }
-  // Lax-Friedrichs speed: the frozen argmax node receives d(|u_d| + c)
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    if (!use[k] || !te[k]) continue;
-    if (qo[k + am[k]] == q) {
-      pb[PB_U + d] += abar[k] * (ud[5] < 0.0 ? -1.0 : 1.0);
-      pb[PB_C] += abar[k];
-    }
-  }
 }
 
 // ------------------------------------------------------------- diffusive
@@ -370,6 +246,270 @@ __device__ __forceinline__ void adj_diff_tangential(const Member& G, const int c
   (void)NV;
 }
 
+// ------------------------------------------------ convective, tiled
+// One 256-node tile per block.  Per direction the tile with a 5-node halo
+// is staged in LDS; every face whose stencil touches the tile takes its
+// hybrid decision and LF speed once, and for each variable its TENO cut-off
+// pattern once (four bits per side, in LDS).  Each node then gathers from
+// the six faces containing it: the face cotangent times the frozen linear
+// coefficient of its stencil position.
+constexpr int EXTA = 896;     // tile extended by 5 + 5 along one axis
+constexpr int FACEA = 640;    // faces touching a tile along one axis
+constexpr int STGA = (EXTA + BLK - 1) / BLK;
+constexpr int FPTA = (FACEA + BLK - 1) / BLK;
+
+template <int NS, int d>
+__device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[3], const int l[3],
+                                                   const int gc[3], bool valid, long long N,
+                                                   const double* __restrict__ U, const double* __restrict__ aux,
+                                                   const unsigned char* __restrict__ flag,
+                                                   const double* __restrict__ lam, double s, unsigned flags,
+                                                   double psi_c, double CT, double* s_ud, double* s_p, double* s_c,
+                                                   double* s_U, double* s_L, double* s_al, unsigned char* s_fl,
+                                                   unsigned char* s_te, unsigned char* s_db, double* s_ub,
+                                                   double& pbu, double& pbp, double& pbc) {
+  constexpr int NV = NS + 4;
+  const int t = threadIdx.x;
+  const int T[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
+  int B[3] = {T[0], T[1], T[2]};
+  B[d] += 10;
+  const int E = B[0] * B[1] * B[2];
+  int FB[3] = {T[0], T[1], T[2]};
+  FB[d] += 5;
+  const int F = FB[0] * FB[1] * FB[2];
+  const int bs = d == 0 ? 1 : (d == 1 ? B[0] : B[0] * B[1]);
+  const int nd = G.n[d];
+  // stage the per-cell fields of the box (box position = tile position + 5 along d)
+  long long qe[STGA];
+#pragma unroll
+  for (int k = 0; k < STGA; ++k) {
+    const int e = t + k * BLK;
+    qe[k] = 0;
+    if (e < E) {
+      const int b[3] = {e % B[0], (e / B[0]) % B[1], e / (B[0] * B[1])};
+      int g[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[a] = wrapi(o[a] + b[a] - (a == d ? 5 : 0), G.n[a]);
+      qe[k] = ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
+      s_ud[e] = aux[(4 + d) * N + qe[k]];
+      s_p[e] = aux[qe[k]];
+      s_c[e] = aux[N + qe[k]];
+      s_fl[e] = flag[qe[k]];
+    }
+  }
+  __syncthreads();
+  // this thread's faces: slot fb_d = j + 2 (0 .. T_d + 4) for the face between tile positions
+  // j-1 and j, whose stencil covers box positions fb_d .. fb_d + 5 along d
+  int fe0[FPTA];
+#pragma unroll
+  for (int k = 0; k < FPTA; ++k) {
+    const int f = t + k * BLK;
+    fe0[k] = -1;
+    if (f < F) {
+      const int fb[3] = {f % FB[0], (f / FB[0]) % FB[1], f / (FB[0] * FB[1])};
+      fe0[k] = fb[0] + B[0] * (fb[1] + B[1] * fb[2]);
+      const int e0 = fe0[k];
+      bool te;
+      if (flags & HTR_FORCE_TENO) te = true;
+      else if (flags & HTR_FORCE_CENTRAL) te = false;
+      else {
+        int any = 0;
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) any |= s_fl[e0 + mm * bs];
+        const double pa = s_p[e0 + 2 * bs], pv = s_p[e0 + 3 * bs];
+        te = any != 0 || fabs(pv - pa) / fmin(pa, pv) > psi_c;
+      }
+      int am = 0;
+      double al = 0.0;
+      if (te) {
+        al = fabs(s_ud[e0]) + s_c[e0];
+#pragma unroll
+        for (int mm = 1; mm < 6; ++mm) {
+          const double sp = fabs(s_ud[e0 + mm * bs]) + s_c[e0 + mm * bs];
+          if (sp > al) { al = sp; am = mm; }
+        }
+      }
+      s_te[f] = (unsigned char)((te ? 1 : 0) | (am << 1));
+      s_al[f] = al;
+    }
+  }
+  // node side: its box index, the six face slots containing it, the metric
+  const int ln[3] = {l[0], l[1], l[2]};
+  const int enode = ln[0] + (d == 0 ? 5 : 0) + B[0] * (ln[1] + (d == 1 ? 5 : 0) + B[1] * (ln[2] + (d == 2 ? 5 : 0)));
+  // the node's faces are slots ln_d + k, k = 0..5 (stencil start ln_d + k - 5 in tile positions);
+  // the node sits at stencil position 5 - k unless the axis is shorter than the stencil
+  const int fs = d == 0 ? 1 : (d == 1 ? FB[0] : FB[0] * FB[1]);
+  const int f0 = ln[0] + FB[0] * (ln[1] + FB[1] * ln[2]);
+  const bool longax = nd >= 6;
+  // short periodic axis: faces revisited (count each once) and several stencil positions per face
+  unsigned use = 0x3f, pos[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    pos[k] = 1u << (5 - k);
+    if (!longax) {
+      const int gf = wrapi(o[d] + ln[d] + k - 2, nd);
+#pragma unroll
+      for (int k2 = 0; k2 < k; ++k2)
+        if (wrapi(o[d] + ln[d] + k2 - 2, nd) == gf) use &= ~(1u << k);
+      pos[k] = 0;
+#pragma unroll
+      for (int mm = 0; mm < 6; ++mm)
+        if (wrapi(o[d] + ln[d] + k - 5 + mm, nd) == gc[d]) pos[k] |= 1u << mm;
+    }
+  }
+  double xi7[7];
+#pragma unroll
+  for (int o7 = 0; o7 < 7; ++o7) xi7[o7] = G.xin[d][wrapi(gc[d] + o7 - 3, nd)];
+  const double C6[6] = {1.0 / 60.0, -8.0 / 60.0, 37.0 / 60.0, 37.0 / 60.0, -8.0 / 60.0, 1.0 / 60.0};
+  const double sg = s_ud[enode] < 0.0 ? -1.0 : 1.0;
+  double abar = 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int k = 0; k < STGA; ++k) {
+      const int e = t + k * BLK;
+      if (e < E) {
+        s_U[e] = U[v * N + qe[k]];
+        s_L[e] = s * lam[v * N + qe[k]];
+      }
+    }
+    __syncthreads();
+    // faces: cut-off bits of the TENO faces
+#pragma unroll
+    for (int k = 0; k < FPTA; ++k) {
+      if (fe0[k] < 0) continue;
+      const int f = t + k * BLK;
+      if (!(s_te[f] & 1)) continue;
+      const int e0 = fe0[k];
+      const double al = s_al[f];
+      double fp[6], fm[6];
+#pragma unroll
+      for (int mm = 0; mm < 6; ++mm) {
+        const int e = e0 + mm * bs;
+        const double u6 = s_U[e], f6 = node_flux<NS>(v, d, u6, s_ud[e], s_p[e]);
+        fp[mm] = 0.5 * (f6 + al * u6);
+        fm[5 - mm] = 0.5 * (f6 - al * u6);
+      }
+      s_db[f] = (unsigned char)(teno6_bits(fp, CT) | (teno6_bits(fm, CT) << 4));
+    }
+    __syncthreads();
+    if (valid) {
+      double Fb = 0.0, Ub = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (!((use >> k) & 1u)) continue;
+        // face between tile positions ln-3+k and ln-2+k: cotangent from its two cells
+        const double g = -xi7[k] * s_L[enode + (k - 3) * bs] + xi7[k + 1] * s_L[enode + (k - 2) * bs];
+        const int f = f0 + k * fs;
+        const unsigned te = s_te[f];
+        if (!(te & 1)) {
+          if (longax) {
+            Fb += g * C6[5 - k];
+          } else {
+#pragma unroll
+            for (int mm = 0; mm < 6; ++mm)
+              if ((pos[k] >> mm) & 1u) Fb += g * C6[mm];
+          }
+        } else {
+          const unsigned bits = s_db[f];
+          double cp[6], cm[6];
+          teno6_coeffs_bits(bits & 15u, cp);
+          teno6_coeffs_bits(bits >> 4, cm);
+          const double al = s_al[f];
+          if (longax) {
+            Fb += g * 0.5 * (cp[5 - k] + cm[k]);
+            Ub += g * 0.5 * al * (cp[5 - k] - cm[k]);
+          } else {
+#pragma unroll
+            for (int mm = 0; mm < 6; ++mm) {
+              if ((pos[k] >> mm) & 1u) {
+                Fb += g * 0.5 * (cp[mm] + cm[5 - mm]);
+                Ub += g * 0.5 * al * (cp[mm] - cm[5 - mm]);
+              }
+            }
+          }
+          // the Lax-Friedrichs speed's frozen argmax node receives d(|u_d| + c)
+          if ((pos[k] >> (te >> 1)) & 1u) {
+            const int e0 = enode + (k - 5) * bs;   // the face's stencil start
+            double da = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < 6; ++mm) da += (cp[mm] - cm[5 - mm]) * s_U[e0 + mm * bs];
+            abar += g * 0.5 * da;
+          }
+        }
+      }
+      const double un = s_ud[enode], un_u = s_U[enode], un_p = s_p[enode];
+      Ub += Fb * un;
+      if (v == NS + 3) {
+        pbu += Fb * (un_u + un_p);
+        pbp += Fb * un;
+      } else {
+        pbu += Fb * un_u;
+        if (v == NS + d) pbp += Fb;
+      }
+      s_ub[v * BLK + t] += Ub;
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    pbu += abar * sg;
+    pbc += abar;
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(BLK, 2) void k_adj_conv_tiled(const Member* __restrict__ mem, int nmem, CallArgs A,
+                                                           const double* __restrict__ Ub,
+                                                           const double* __restrict__ auxb,
+                                                           const unsigned char* __restrict__ flagb,
+                                                           const double* __restrict__ lamb, double s,
+                                                           double* __restrict__ ubdb, double* __restrict__ pbb,
+                                                           double psi_c, double CT) {
+  constexpr int NV = NS + 4, NAUX = 7 + NS, NPB = 8 + NS;
+  __shared__ double s_ud[EXTA], s_p[EXTA], s_c[EXTA], s_U[EXTA], s_L[EXTA], s_al[FACEA];
+  __shared__ unsigned char s_fl[EXTA], s_te[FACEA], s_db[FACEA];
+  __shared__ double s_ub[NV * BLK];   // per-thread cotangent accumulators
+  const int m = find_member_tiled(mem, nmem, blockIdx.x);
+  const Member& G = mem[m];
+  const int t = threadIdx.x;
+  int o[3];
+  tile_origin(G, blockIdx.x - G.tblock_begin, o);
+  const int T0 = G.tdim[0], T1 = G.tdim[1];
+  const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
+  const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+  const bool valid = gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
+  const long long N = G.N;
+  const double* U = Ub + NV * G.off;
+  const double* aux = auxb + NAUX * G.off;
+  const unsigned char* flag = flagb + G.off;
+  const double* lam = lamb + NV * G.off;
+  for (int v = 0; v < NV; ++v) s_ub[v * BLK + t] = 0.0;
+  double pbu[3] = {0.0, 0.0, 0.0}, pbp = 0.0, pbc = 0.0;
+  const unsigned flags = A.flags;
+  if (G.act[0])
+    adj_conv_tiled_dir<NS, 0>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[0], pbp, pbc);
+  if (G.act[1])
+    adj_conv_tiled_dir<NS, 1>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[1], pbp, pbc);
+  if (G.act[2])
+    adj_conv_tiled_dir<NS, 2>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[2], pbp, pbc);
+  if (!valid) return;
+  const long long q = ((long long)gc[2] * G.n[1] + gc[1]) * G.n[0] + gc[0];
+  double* ubd = ubdb + NV * G.off;
+  double* pbo = pbb + NPB * G.off;
+  for (int v = 0; v < NV; ++v) ubd[v * N + q] = s_ub[v * BLK + t];
+  for (int k = 0; k < NPB; ++k) {
+    double x = 0.0;
+    if (k == PB_P) x = pbp;
+    else if (k == PB_C) x = pbc;
+    else if (k >= PB_U && k < PB_U + 3) x = pbu[k - PB_U];
+    pbo[k * N + q] = x;
+  }
+}
+
 // All diffusive contributions of direction d to a node: the two faces of
 // which it is a node, and the faces of which it is a tangential neighbour.
 template <int NS, int d>
@@ -389,16 +529,13 @@ __device__ __forceinline__ void adj_diff_dir(const MechTables* __restrict__ M, c
   if (G.act[t2]) adj_diff_tangential<NS, d, t2>(G, c, q, N, aux, lam, s, pb);
 }
 
-// PART 0: convective faces (writes the cotangents); PART 1: diffusive faces
-// (adds to them).  Two kernels keep each one's register footprint small.
-template <int NS, int PART>
-__global__ __launch_bounds__(BLK) void k_adj_sweep(const MechTables* __restrict__ M, const Member* __restrict__ mem,
-                                                   int nmem, CallArgs A, const double* __restrict__ Ub,
-                                                   const double* __restrict__ Tb, const double* __restrict__ auxb,
-                                                   const unsigned char* __restrict__ flagb,
-                                                   const double* __restrict__ lamb, double s,
-                                                   double* __restrict__ ubdb, double* __restrict__ pbb,
-                                                   double psi_c, double CT) {
+// Diffusive faces: one thread per node, adds to the convective cotangents.
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_adj_diff(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                  int nmem, const double* __restrict__ Ub,
+                                                  const double* __restrict__ Tb, const double* __restrict__ auxb,
+                                                  const double* __restrict__ lamb, double s,
+                                                  double* __restrict__ ubdb, double* __restrict__ pbb) {
   constexpr int NV = NS + 4, NAUX = 7 + NS, NPB = 8 + NS;
   const int m = find_member(mem, nmem, blockIdx.x);
   const Member& G = mem[m];
@@ -408,27 +545,18 @@ __global__ __launch_bounds__(BLK) void k_adj_sweep(const MechTables* __restrict_
   const double* U = Ub + NV * G.off;
   const double* T = Tb + G.off;
   const double* aux = auxb + NAUX * G.off;
-  const unsigned char* flag = flagb + G.off;
   const double* lam = lamb + NV * G.off;
   const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
-  const long long strides[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
   double ubar[NV], pb[NPB];
   double* ubd = ubdb + NV * G.off;
   double* pbo = pbb + NPB * G.off;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) ubar[v] = PART ? ubd[v * N + q] : 0.0;
+  for (int v = 0; v < NV; ++v) ubar[v] = ubd[v * N + q];
 #pragma unroll
-  for (int k = 0; k < NPB; ++k) pb[k] = PART ? pbo[k * N + q] : 0.0;
-  const unsigned flags = A.flags;
-  if (PART == 0) {
-    if (G.act[0]) adj_conv<NS, 0>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
-    if (G.act[1]) adj_conv<NS, 1>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
-    if (G.act[2]) adj_conv<NS, 2>(G, c, q, N, U, aux, flag, lam, s, flags, psi_c, CT, ubar, pb);
-  } else if (!(flags & HTR_VISC_OFF)) {
-    if (G.act[0]) adj_diff_dir<NS, 0>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
-    if (G.act[1]) adj_diff_dir<NS, 1>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
-    if (G.act[2]) adj_diff_dir<NS, 2>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
-  }
+  for (int k = 0; k < NPB; ++k) pb[k] = pbo[k * N + q];
+  if (G.act[0]) adj_diff_dir<NS, 0>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
+  if (G.act[1]) adj_diff_dir<NS, 1>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
+  if (G.act[2]) adj_diff_dir<NS, 2>(M, G, c, q, N, U, T, aux, lam, s, ubar, pb);
 #pragma unroll
   for (int v = 0; v < NV; ++v) ubd[v * N + q] = ubar[v];
 #pragma unroll
@@ -842,17 +970,17 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
 }
 
 template <int NS>
-static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
+                        const CallArgs& a,
                         const double* U, const double* T, const double* aux, const unsigned char* flag,
                         const double* lam, double s, double h, double* ubd, double* pbv, double* out,
                         double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
-  hipLaunchKernelGGL((k_adj_sweep<NS, 0>), dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam, s,
+  hipLaunchKernelGGL((k_adj_conv_tiled<NS>), dim3(ntblocks), dim3(BLK), 0, st, mem, nmem, a, U, aux, flag, lam, s,
                      ubd, pbv, psi_c, CT);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!(a.flags & HTR_VISC_OFF)) {
-    hipLaunchKernelGGL((k_adj_sweep<NS, 1>), dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, a, U, T, aux, flag, lam,
-                       s, ubd, pbv, psi_c, CT);
+    hipLaunchKernelGGL(k_adj_diff<NS>, dim3(nblocks), dim3(BLK), 0, st, M, mem, nmem, U, T, aux, lam, s, ubd, pbv);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -861,11 +989,13 @@ static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nb
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
+                          const CallArgs& a,
                           const double* U, const double* T, const double* aux, const unsigned char* flag,
                           const double* lam, double s, double h, double* ubd, double* pbv, double* out,
                           double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
-#define C_(NS) adj_t<NS>(M, mem, nmem, nblocks, a, U, T, aux, flag, lam, s, h, ubd, pbv, out, thpart, nth, psi_c, CT, st)
+#define C_(NS) \
+  adj_t<NS>(M, mem, nmem, nblocks, ntblocks, a, U, T, aux, flag, lam, s, h, ubd, pbv, out, thpart, nth, psi_c, CT, st)
   switch (ns) {
     case 1: return C_(1); case 2: return C_(2); case 3: return C_(3);
     case 4: return C_(4); case 5: return C_(5); case 6: return C_(6);

@@ -55,7 +55,7 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
   HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, nullptr,
                        st));
   const int nth = 4 + c->nr;
-  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T, c->ws.aux, c->ws.flag, lam, s, h, b.ubd, b.pb,
+  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, T, c->ws.aux, c->ws.flag, lam, s, h, b.ubd, b.pb,
                         out, b.thpart, nth, C.scheme.psi_c, C.scheme.teno_CT, st));
   HIP_OK(launch_adj_theta(C.mem, 1, b.thpart, nth, pbar, st));
   return HTR_OK;

@@ -257,7 +257,7 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
   HIP_OK(hipEventRecord(b->ev_in, s));
   HIP_OK(hipStreamWaitEvent(b->gstream, b->ev_in, 0));
   {
-    TimedLaunch tl(&b->timer, 3, b->gstream);
+    TimedLaunch tl(&b->timer, TC_REDUCE, b->gstream);
     HIP_OK(hipGraphLaunch(b->exec, b->gstream));
   }
   HIP_OK(hipEventRecord(b->ev_out, b->gstream));

@@ -239,22 +239,27 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
                  double jcoef, hipStream_t s, int want_dt, double* dt_out) {
   const bool need_red = J_dev != nullptr || want_dt;
   {
-    TimedLaunch tl(C.timer, 0, s);
+    TimedLaunch tl(C.timer, TC_POINT, s);
     HIP_OK(launch_point(C.ns, C.M, C.mem, C.nmem, C.nblocks, a, U, T, w.aux, w.src, hrr,
                         need_red ? w.blkred : nullptr, nullptr, w.status, want_dt, s));
   }
   if (need_red) {
-    TimedLaunch tl(C.timer, 3, s);
+    TimedLaunch tl(C.timer, TC_REDUCE, s);
     HIP_OK(launch_finalize(C.mem, C.nmem, w.blkred, C.scheme.cfl, dt_out, J_dev, a.dt_dev, jcoef, want_dt, s));
   }
   {
-    TimedLaunch tl(C.timer, 1, s);
+    TimedLaunch tl(C.timer, TC_SENSOR, s);
     HIP_OK(launch_sensor(C.mem, C.nmem, C.nblocks, w.aux, C.ns, w.flag, w.grad, C.scheme.theta_c, nullptr, s));
   }
   {
-    TimedLaunch tl(C.timer, 2, s);
-    HIP_OK(launch_sweep(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, Un, T, w.aux, w.src, w.flag, w.grad, w.part,
-                        out, ca, cb, rhs_only, C.scheme.psi_c, C.scheme.teno_CT, s));
+    TimedLaunch tl(C.timer, TC_CONV, s);
+    HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, w.aux, w.src, w.flag, w.part, C.scheme.psi_c,
+                       C.scheme.teno_CT, s));
+  }
+  {
+    TimedLaunch tl(C.timer, TC_DIFF, s);
+    HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, Un, T, w.aux, w.grad, w.part, out, ca, cb,
+                       rhs_only, s));
   }
   return HTR_OK;
 }
@@ -284,7 +289,7 @@ htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t
                           k == 0 && compute_dt, dt_dev);
     if (st) return st;
   }
-  TimedLaunch tl(C.timer, 3, s);
+  TimedLaunch tl(C.timer, TC_REDUCE, s);
   HIP_OK(launch_advance_time(C.nmem, t_dev, dt_dev, s));
   return HTR_OK;
 }
@@ -504,7 +509,7 @@ htr_status htr_timing(htr_ctx* c, int enable) {
 
 htr_status htr_timing_read(htr_ctx* c, double* ms, int64_t* launches) {
   if (!c || !ms || !launches) return fail(HTR_EINVAL, "NULL pointer");
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < HTR_TIMING_CLASSES; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
   }

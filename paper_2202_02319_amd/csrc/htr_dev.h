@@ -125,6 +125,16 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Dispatch on the species count (the kernels are templated on it).
+#define HTR_NS_SWITCH(ns, CALL)                                                        \
+  switch (ns) {                                                                        \
+    case 1: return CALL(1); case 2: return CALL(2); case 3: return CALL(3);            \
+    case 4: return CALL(4); case 5: return CALL(5); case 6: return CALL(6);            \
+    case 7: return CALL(7); case 8: return CALL(8); case 9: return CALL(9);            \
+    case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12);      \
+    default: return hipErrorInvalidValue;                                              \
+  }
+
 // host-side launchers (defined in the .hip files)
 struct Workspace;
 hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
@@ -135,16 +145,19 @@ hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem
                         double* cells_out, unsigned* status, int want_dt, hipStream_t s);
 hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
                          double* grad, double theta_c, double* theta_out, hipStream_t s);
-hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
-                        const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                        const unsigned char* flag, const double* grad, double* part, double* out, double ca,
-                        double cb, int rhs_only, double psi_c, double CT, hipStream_t s);
+hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                       const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
+                       double psi_c, double CT, hipStream_t s);
+hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                       const double* U, const double* Un, const double* T, const double* aux, const double* grad,
+                       const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s);
 // tile shape and tiled-block count of a member (host side)
 void set_tiles(Member& M, int* tblocks);
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);
-hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
+                          const CallArgs& a,
                           const double* U, const double* T, const double* aux, const unsigned char* flag,
                           const double* lam, double s, double h, double* ubd, double* pbv, double* out,
                           double* thpart, int nth, double psi_c, double CT, hipStream_t st);

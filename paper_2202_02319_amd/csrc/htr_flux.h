@@ -75,6 +75,28 @@ __device__ __forceinline__ void teno6_coeffs(const double f[6], double CT, doubl
   c[5] = w[3] * (1.0 / 12.0);
 }
 
+// Cut-off pattern of teno6_core as four bits (bit k: candidate k kept).
+__device__ __forceinline__ unsigned teno6_bits(const double f[6], double CT) {
+  double w[4], q[4];
+  teno6_core(f, CT, w, q);
+  return (w[0] > 0.0 ? 1u : 0u) | (w[1] > 0.0 ? 2u : 0u) | (w[2] > 0.0 ? 4u : 0u) | (w[3] > 0.0 ? 8u : 0u);
+}
+
+// Linear coefficients of the frozen reconstruction from its cut-off bits
+// (the same normalised weights teno6_core produces for that pattern).
+__device__ __forceinline__ void teno6_coeffs_bits(unsigned b, double c[6]) {
+  double w0 = (b & 1u) ? 9.0 / 20.0 : 0.0, w1 = (b & 2u) ? 3.0 / 10.0 : 0.0;
+  double w2 = (b & 4u) ? 1.0 / 20.0 : 0.0, w3 = (b & 8u) ? 1.0 / 5.0 : 0.0;
+  const double iw = 1.0 / (w0 + w1 + w2 + w3);
+  w0 *= iw; w1 *= iw; w2 *= iw; w3 *= iw;
+  c[0] = w2 * (2.0 / 6.0);
+  c[1] = w0 * (-1.0 / 6.0) + w2 * (-7.0 / 6.0);
+  c[2] = w0 * (5.0 / 6.0) + w1 * (2.0 / 6.0) + w2 * (11.0 / 6.0) + w3 * (3.0 / 12.0);
+  c[3] = w0 * (2.0 / 6.0) + w1 * (5.0 / 6.0) + w3 * (13.0 / 12.0);
+  c[4] = w1 * (-1.0 / 6.0) + w3 * (-5.0 / 12.0);
+  c[5] = w3 * (1.0 / 12.0);
+}
+
 // Node convective flux of variable v along d (u_d normal velocity, p pressure).
 template <int NS>
 __device__ __forceinline__ double node_flux(int v, int d, double U, double ud, double p) {

@@ -33,6 +33,9 @@ struct Workspace {
   double* scal = nullptr;         // [2][nmem] scratch scalars
 };
 
+// Timing classes (the order of htr_timing_read's arrays).
+enum { TC_POINT = 0, TC_SENSOR = 1, TC_CONV = 2, TC_DIFF = 3, TC_REDUCE = 4 };
+
 // HIP-event kernel timer (diagnostics).
 struct Timer {
   bool on = false;

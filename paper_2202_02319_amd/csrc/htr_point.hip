@@ -458,15 +458,6 @@ static hipError_t point_t(const MechTables* M, const Member* mem, int nmem, int 
   return hipGetLastError();
 }
 
-#define HTR_NS_SWITCH(ns, CALL)                                                        \
-  switch (ns) {                                                                        \
-    case 1: return CALL(1); case 2: return CALL(2); case 3: return CALL(3);            \
-    case 4: return CALL(4); case 5: return CALL(5); case 6: return CALL(6);            \
-    case 7: return CALL(7); case 8: return CALL(8); case 9: return CALL(9);            \
-    case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12);      \
-    default: return hipErrorInvalidValue;                                              \
-  }
-
 hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
                                const double* Y, const double* T, const double* p, const double* vel, double* U,
                                hipStream_t s) {

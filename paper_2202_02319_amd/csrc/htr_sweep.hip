@@ -399,32 +399,36 @@ __global__ __launch_bounds__(BLK, 3) void k_diff(const MechTables* __restrict__ 
 }
 
 template <int NS>
-static hipError_t sweep_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
-                          const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                          const unsigned char* flag, const double* grad, double* part, double* out, double ca,
-                          double cb, int rhs_only, double psi_c, double CT, hipStream_t s) {
+static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                         const double* U, const double* aux, const double* src, const unsigned char* flag,
+                         double* part, double psi_c, double CT, hipStream_t s) {
   hipLaunchKernelGGL(k_conv<NS>, dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part, psi_c,
                      CT);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t diff_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                         const double* U, const double* Un, const double* T, const double* aux, const double* grad,
+                         const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
   hipLaunchKernelGGL(k_diff<NS>, dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, Un, T, aux, grad, part, out,
                      ca, cb, rhs_only);
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
-                        const double* U, const double* Un, const double* T, const double* aux, const double* src,
-                        const unsigned char* flag, const double* grad, double* part, double* out, double ca,
-                        double cb, int rhs_only, double psi_c, double CT, hipStream_t s) {
-#define C_(NS) sweep_t<NS>(M, mem, nmem, ntblocks, a, U, Un, T, aux, src, flag, grad, part, out, ca, cb, rhs_only, \
-                           psi_c, CT, s)
-  switch (ns) {
-    case 1: return C_(1); case 2: return C_(2); case 3: return C_(3);
-    case 4: return C_(4); case 5: return C_(5); case 6: return C_(6);
-    case 7: return C_(7); case 8: return C_(8); case 9: return C_(9);
-    case 10: return C_(10); case 11: return C_(11); case 12: return C_(12);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                       const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
+                       double psi_c, double CT, hipStream_t s) {
+#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, a, U, aux, src, flag, part, psi_c, CT, s)
+  HTR_NS_SWITCH(ns, C_);
+#undef C_
+}
+
+hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+                       const double* U, const double* Un, const double* T, const double* aux, const double* grad,
+                       const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
+#define C_(NS) diff_t<NS>(M, mem, nmem, ntblocks, a, U, Un, T, aux, grad, part, out, ca, cb, rhs_only, s)
+  HTR_NS_SWITCH(ns, C_);
 #undef C_
 }
 

@@ -160,15 +160,16 @@ def htr_timing(ctx, enable):
     check(ctx.lib.htr_timing(ctx.h, int(enable)))
 
 
-KERNEL_CLASSES = ("point", "sensor", "sweep", "reduce")
+KERNEL_CLASSES = ("point", "sensor", "conv", "diff", "reduce")
 
 
 def htr_timing_read(ctx):
     """{class: (total ms, launches)} since htr_timing(ctx, 1)."""
-    ms = (C.c_double * 4)()
-    n = (C.c_int64 * 4)()
+    nc = len(KERNEL_CLASSES)
+    ms = (C.c_double * nc)()
+    n = (C.c_int64 * nc)()
     check(ctx.lib.htr_timing_read(ctx.h, ms, n))
-    return {KERNEL_CLASSES[k]: (ms[k], n[k]) for k in range(4)}
+    return {KERNEL_CLASSES[k]: (ms[k], n[k]) for k in range(nc)}
 
 
 def htr_adjoint_work_bytes(ctx):

@@ -20,6 +20,9 @@ CASES = [
     ("1d", dict(n=(24, 1, 1), seed=34), 0),
     ("tiny", dict(n=(5, 4, 3), seed=35), synth.FORCE_TENO),
     ("3d-central-novisc", dict(n=(8, 6, 5), seed=36), synth.FORCE_CENTRAL | synth.VISC_OFF),
+    # several ragged tiles along every axis (tiles are 16 x 4 x 4 cells)
+    ("3d-multitile-teno", dict(n=(21, 9, 7), seed=37), synth.FORCE_TENO),
+    ("3d-multitile", dict(n=(21, 9, 7), seed=38), 0),
 ]
 
 
