@@ -111,10 +111,21 @@ __device__ __forceinline__ int find_member_tiled(const Member* __restrict__ mem,
 // Tile origin of local tiled block bl.  Blocks are dealt to the eight XCDs
 // round-robin; the first 8*(nb/8) blocks are remapped so that each XCD works
 // on one contiguous run of tiles and neighbouring tiles share its L2.
+constexpr int TILE_ZGROUP = 4;
 __device__ __forceinline__ void tile_origin(const Member& G, int bl, int o[3]) {
   const int nb = G.ntblocks, per = nb >> 3;
   const int lb = bl < 8 * per ? (bl & 7) * per + (bl >> 3) : bl;
-  const int tx = lb % G.ntile[0], ty = (lb / G.ntile[0]) % G.ntile[1], tz = lb / (G.ntile[0] * G.ntile[1]);
+  // lb -> tile: x fastest, then z within groups of TILE_ZGROUP tile layers, then
+  // y, then the z group, so that tiles adjacent in y and z are processed
+  // close together in time (only the last group may be thinner)
+  const int ntx = G.ntile[0], nty = G.ntile[1], ntz = G.ntile[2];
+  const int gz = ntz < TILE_ZGROUP ? ntz : TILE_ZGROUP;
+  const int per_group = ntx * nty * gz;
+  const int grp = lb / per_group;
+  const int gsz = ntz - grp * gz < gz ? ntz - grp * gz : gz;
+  const int r = lb - grp * per_group;
+  const int tx = r % ntx, r2 = r / ntx;
+  const int tz = grp * gz + r2 % gsz, ty = r2 / gsz;
   o[0] = tx * G.tdim[0];
   o[1] = ty * G.tdim[1];
   o[2] = tz * G.tdim[2];
