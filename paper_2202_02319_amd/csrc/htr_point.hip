@@ -93,7 +93,7 @@ __global__ __launch_bounds__(BLK) void k_prim_to_cons(const MechTables* __restri
 // aux rows per cell: 0 p, 1 c, 2 mu, 3 lambda, 4..6 velocity, 7.. D_s.
 // src rows: 0..NS-1 wdot_s, NS q_L.  blkred per block: {sum dV hrr, min dt limit}.
 template <int NS>
-__global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+__global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                                int nmem, CallArgs A, const double* __restrict__ Ub,
                                                double* __restrict__ Tb, double* __restrict__ auxb,
                                                double* __restrict__ srcb, double* __restrict__ hrrb,
@@ -122,6 +122,8 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
       r[s] = U[s * N + q];
       rho += r[s];
       finite = finite && isfinite(r[s]);
+      // molar concentrations for the reaction products (per-thread LDS column)
+      conc[s][tid] = r[s] * M->iW[s];
     }
     const double mx = U[NS * N + q], my = U[(NS + 1) * N + q], mz = U[(NS + 2) * N + q];
     const double E = U[(NS + 3) * N + q];
@@ -181,6 +183,11 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
     const double Wm = 1.0 / iWm;
     const double p = rho * RU * T * iWm;
     const double c = sqrt(cp / (cp - RU * iWm) * p * irho);
+    aux[0 * N + q] = p;
+    aux[1 * N + q] = c;
+    aux[4 * N + q] = u;
+    aux[5 * N + q] = v;
+    aux[6 * N + q] = w;
     double X[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) X[s] = Y[s] * Wm * M->iW[s];
@@ -189,29 +196,33 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
     // (T/eps)^-b = T^-b eps^b, one exponential per cell for each fit.
     const double lnT = log(T), sqT = sqrt(T);
     const double Tb22 = exp(-0.14874 * lnT), Tb11 = exp(-0.15610 * lnT);
-    double mus[NS], lams[NS], smu[NS], ismu[NS];
+    // (lambda_s and sqrt(mu_s) are formed where they are used, so that only
+    // mu_s and 1/sqrt(mu_s) are held for all species)
+    double mus[NS], ismu[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double Ts = T * M->ieps[s];
       const double o22 = 1.16145 * (Tb22 * M->pw22[s]) + 0.52487 * exp(-0.77320 * Ts) + 2.16178 * exp(-2.43787 * Ts);
       mus[s] = M->mu_pre[s] * sqT / o22;
-      lams[s] = mus[s] * (M->RW[s] * cpR(M, s, T) + M->euck[s]);
-      smu[s] = sqrt(mus[s]);
-      ismu[s] = 1.0 / smu[s];
+      ismu[s] = 1.0 / sqrt(mus[s]);
     }
     double mu = 0.0, lam = 0.0;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
+      const double smu = sqrt(mus[i]);
       double den = 0.0;
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
-        const double t1 = 1.0 + smu[i] * ismu[j] * M->wq[i][j];
+        const double t1 = 1.0 + smu * ismu[j] * M->wq[i][j];
         den += X[j] * (t1 * t1 * M->wp[i][j]);
       }
       const double id = 1.0 / den;
+      const double lams = mus[i] * (M->RW[i] * cpR(M, i, T) + M->euck[i]);
       mu += X[i] * mus[i] * id;
-      lam += X[i] * lams[i] * id;
+      lam += X[i] * lams * id;
     }
+    aux[2 * N + q] = mu;
+    aux[3 * N + q] = lam;
     double Dacc[NS], Ds[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) Dacc[s] = 0.0;
@@ -237,13 +248,6 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
         Ds[s] = (1.0 - Y[s]) / Dacc[s];
       }
     }
-    aux[0 * N + q] = p;
-    aux[1 * N + q] = c;
-    aux[2 * N + q] = mu;
-    aux[3 * N + q] = lam;
-    aux[4 * N + q] = u;
-    aux[5 * N + q] = v;
-    aux[6 * N + q] = w;
 #pragma unroll
     for (int s = 0; s < NS; ++s) aux[(7 + s) * N + q] = Ds[s];
 
@@ -255,10 +259,7 @@ __global__ __launch_bounds__(BLK) void k_point(const MechTables* __restrict__ M,
     if (!(flags & HTR_CHEM_OFF)) {
       double Gs[NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        conc[s][tid] = r[s] * M->iW[s];
-        Gs[s] = hRT(M, s, T, iT) - sR(M, s, T, lnT);
-      }
+      for (int s = 0; s < NS; ++s) Gs[s] = hRT(M, s, T, iT) - sR(M, s, T, lnT);
       const double lnP = log(PREF / (RU * T));
       const double* dlnA = A.dlnA ? A.dlnA : G.dlnA;
       const int nr = M->nr;

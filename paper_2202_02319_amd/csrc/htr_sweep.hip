@@ -63,169 +63,264 @@ __device__ __attribute__((noinline)) double teno_face(double f0, double f1, doub
 }
 
 constexpr int BLKF = 320;        // threads of the diffusive sweep: one per face of a tile along an axis
-constexpr int EXT_MAX = 640;     // tile extended by 3 + 3 cells along one axis
-constexpr int FACE_MAX = 320;    // faces of a tile along one axis
-constexpr int STG = (EXT_MAX + BLK - 1) / BLK;
-constexpr int FPT = (FACE_MAX + BLK - 1) / BLK;
 
 __device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
   return ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
 }
 
+// Cross staging of the convective sweep: the tile plus a 3-cell halo on both
+// sides along every active axis.  Each staged value is loaded once and
+// written into the line-contiguous box of every direction that uses it (the
+// tile's own cells into all of them).
+constexpr int XBOX_MAX = 2208;   // three direction boxes of a 16x4x4 tile: 22*4*4 + 16*10*4 + 16*4*10
+constexpr int XARM_MAX = 864;    // halo cells: 6 per line along every axis
+constexpr int XFACE_MAX = 912;   // faces over all axes: 17*4*4 + 16*5*4 + 16*4*5
+constexpr int APT = (XARM_MAX + BLK - 1) / BLK;
+constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
+
 // Sources plus convective flux differences of every active direction, per
-// cell, into part[nv][N].  Per direction the tile and a 3-cell halo along
-// that direction are staged in LDS (velocity, pressure, sound speed, sensor
-// flag, then one conserved variable at a time); every face is evaluated
-// once: its hybrid decision and Lax-Friedrichs speed once for all
-// variables, then its flux for each variable.
+// cell, into part[nv][N].  The sensor flag, pressure and LF node speed of the
+// cross are staged once and every face of the tile takes its hybrid decision
+// and Lax-Friedrichs speed once for all variables.  Then, per conserved
+// variable, each staged cell's value and its node flux along each axis are
+// written once (the loading thread keeps that cell's velocity and pressure
+// in registers), and every face flux is evaluated once from them, all
+// directions together.
 template <int NS>
-__global__ __launch_bounds__(BLK, 3) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+__global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                               int nmem, CallArgs A, const double* __restrict__ Ub,
                                               const double* __restrict__ auxb, const double* __restrict__ srcb,
                                               const unsigned char* __restrict__ flagb, double* __restrict__ partb,
                                               double psi_c, double CT) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
-  // staged arrays padded to STG * BLK so the staging loop needs no bounds
-  // branch (entries past the box are written and never read)
-  __shared__ double s_ud[STG * BLK], s_p[STG * BLK], s_c[STG * BLK], s_U[2][STG * BLK], s_F[2][FACE_MAX];
-  __shared__ unsigned char s_fl[STG * BLK];
+  // one spare slot past every box: a write target for threads without a halo cell
+  __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
+  // before the variable loop the same memory holds the LF node speed, the
+  // pressure and the sensor flags
+  double* s_spd = s_U;
+  double* s_p = s_Fn;
+  unsigned char* s_fl = reinterpret_cast<unsigned char*>(&s_F[0][0]);
   const int m = find_member_tiled(mem, nmem, blockIdx.x);
   const Member& G = mem[m];
   const int t = threadIdx.x;
   int o[3];
   tile_origin(G, blockIdx.x - G.tblock_begin, o);
-  const int T0 = G.tdim[0], T1 = G.tdim[1], T2 = G.tdim[2];
-  const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
+  const int T[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
+  const int TT = T[0] * T[1] * T[2];
+  const bool act[3] = {G.act[0] != 0, G.act[1] != 0, G.act[2] != 0};
+  // layout of the boxes, the halo cells and the faces
+  int boff[3], foff[3], aoff[3];
+  int Ftot, Atot;
+  {
+    int eo = 0, fo = 0, ao = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      boff[d] = eo;
+      foff[d] = fo;
+      aoff[d] = ao;
+      if (act[d]) {
+        eo += TT / T[d] * (T[d] + 6);
+        fo += TT / T[d] * (T[d] + 1);
+        ao += 6 * (TT / T[d]);
+      }
+    }
+    Ftot = fo;
+    Atot = ao;
+  }
+  // slot of box position b in box d
+  auto bslot = [&](int d, int b0, int b1, int b2) {
+    const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
+    return boff[d] + b0 + B0 * (b1 + B1 * b2);
+  };
+  // this thread's cell
+  const int l[3] = {t % T[0], (t / T[0]) % T[1], t / (T[0] * T[1])};
   const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
   const bool valid = gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
   const long long N = G.N;
   const double* U = Ub + NV * G.off;
   const double* aux = auxb + NAUX * G.off;
   const unsigned char* flag = flagb + G.off;
-  const long long q = valid ? lin(G, gc) : 0;
-  double acc[NV];
   const double* src = srcb + (NS + 1) * G.off;
+  long long qc;
+  {
+    int g[3];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  if (valid) {
-#pragma unroll
-    for (int v = 0; v < NS; ++v) acc[v] = src[v * N + q];
-    acc[NS + 3] = src[NS * N + q];
+    for (int a = 0; a < 3; ++a) g[a] = wrapi(gc[a], G.n[a]);
+    qc = lin(G, g);
   }
-  const unsigned flags = A.flags;
-  for (int d = 0; d < 3; ++d) {
-    if (!G.act[d]) continue;
-    int B[3] = {T0, T1, T2};
-    B[d] += 6;
-    const int E = B[0] * B[1] * B[2];
-    int FB[3] = {T0, T1, T2};
-    FB[d] += 1;
-    const int F = FB[0] * FB[1] * FB[2];
-    const int bstride = d == 0 ? 1 : (d == 1 ? B[0] : B[0] * B[1]);
-    // stage per-cell fields of the extended box; keep the global indices
-    // (slots past the box load the box's last cell: in bounds, never read)
-    long long qe[STG];
+  int cs[3];
 #pragma unroll
-    for (int k = 0; k < STG; ++k) {
-      const int e = t + k * BLK, ec = e < E ? e : E - 1;
-      const int b[3] = {ec % B[0], (ec / B[0]) % B[1], ec / (B[0] * B[1])};
+  for (int d = 0; d < 3; ++d)
+    cs[d] = act[d] ? bslot(d, l[0] + (d == 0 ? 3 : 0), l[1] + (d == 1 ? 3 : 0), l[2] + (d == 2 ? 3 : 0))
+                   : XBOX_MAX;
+  // this thread's halo cells (box slot, global index, axis)
+  int as[APT], ax[APT];
+  long long aq[APT];
+#pragma unroll
+  for (int k = 0; k < APT; ++k) {
+    const int a = t + k * BLK;
+    as[k] = XBOX_MAX;
+    aq[k] = qc;
+    ax[k] = 0;
+    if (a < Atot) {
+      const int d = a < aoff[1] ? 0 : (a < aoff[2] ? 1 : 2);
+      const int r = a - aoff[d], S = TT / T[d];
+      const int j6 = r / S, cidx = r % S;
+      const int side = j6 / 3, j = j6 - 3 * side;
+      int lc[3];
+      lc[d] = side == 0 ? j - 3 : T[d] + j;
+      const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;   // the two other axes, in order
+      lc[e1] = cidx % T[e1];
+      lc[e2] = cidx / T[e1];
       int g[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) g[a] = wrapi(o[a] + b[a] - (a == d ? 3 : 0), G.n[a]);
-      qe[k] = lin(G, g);
-      s_ud[e] = aux[(4 + d) * N + qe[k]];
-      s_p[e] = aux[qe[k]];
-      s_c[e] = aux[N + qe[k]];
-      s_fl[e] = flag[qe[k]];
+      for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + lc[c], G.n[c]);
+      aq[k] = lin(G, g);
+      ax[k] = d;
+      int b[3] = {lc[0], lc[1], lc[2]};
+      b[d] += 3;
+      as[k] = bslot(d, b[0], b[1], b[2]);
     }
-    __syncthreads();
-    // this thread's faces: hybrid decision and LF speed
-    int fe0[FPT];
-    bool fte[FPT];
-    double fal[FPT];
-#pragma unroll
-    for (int k = 0; k < FPT; ++k) {
-      const int f = t + k * BLK;
-      fe0[k] = -1;
-      fte[k] = false;
-      fal[k] = 0.0;
-      if (f < F) {
-        const int fb[3] = {f % FB[0], (f / FB[0]) % FB[1], f / (FB[0] * FB[1])};
-        // stencil positions j-3..j+2 of the tile = box positions j..j+5 along d
-        fe0[k] = fb[0] + B[0] * (fb[1] + B[1] * fb[2]);
-        const int e0 = fe0[k];
-        bool te;
-        if (flags & HTR_FORCE_TENO) te = true;
-        else if (flags & HTR_FORCE_CENTRAL) te = false;
-        else {
-          int any = 0;
-#pragma unroll
-          for (int mm = 0; mm < 6; ++mm) any |= s_fl[e0 + mm * bstride];
-          const double pa = s_p[e0 + 2 * bstride], pb = s_p[e0 + 3 * bstride];
-          const double psi = fabs(pb - pa) / fmin(pa, pb);
-          te = any != 0 || psi > psi_c;
-        }
-        fte[k] = te;
-        if (te) {
-          double al = fabs(s_ud[e0]) + s_c[e0];
-#pragma unroll
-          for (int mm = 1; mm < 6; ++mm) al = fmax(al, fabs(s_ud[e0 + mm * bstride]) + s_c[e0 + mm * bstride]);
-          fal[k] = al;
-        }
-      }
-    }
-    int lf[3] = {l[0], l[1], l[2]};
-    const int fL = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
-    lf[d] += 1;
-    const int fR = lf[0] + FB[0] * (lf[1] + FB[1] * lf[2]);
-    const double xi = valid ? G.xin[d][gc[d]] : 0.0;
-    // software pipeline: the next variable's staging loads are in flight
-    // while the current variable's faces are evaluated (double-buffered LDS)
-    double nxt[STG];
-#pragma unroll
-    for (int k = 0; k < STG; ++k) nxt[k] = U[qe[k]];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double* sU = s_U[v & 1];
-      double* sF = s_F[v & 1];
-#pragma unroll
-      for (int k = 0; k < STG; ++k) sU[t + k * BLK] = nxt[k];
-      if (v + 1 < NV) {
-#pragma unroll
-        for (int k = 0; k < STG; ++k) nxt[k] = U[(v + 1) * N + qe[k]];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < FPT; ++k) {
-        if (fe0[k] < 0) continue;
-        const int e0 = fe0[k];
-        double f6[6], u6[6];
-#pragma unroll
-        for (int mm = 0; mm < 6; ++mm) {
-          const int e = e0 + mm * bstride;
-          u6[mm] = sU[e];
-          f6[mm] = node_flux<NS>(v, d, u6[mm], s_ud[e], s_p[e]);
-        }
-        double Fh;
-        if (!fte[k]) {
-          // the face value goes through LDS before it is differenced, so its
-          // last rounding cannot be fused into the difference
-          Fh = (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
-        } else {
-          Fh = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4], u6[5],
-                         fal[k], CT);
-        }
-        sF[t + k * BLK] = Fh;
-      }
-      __syncthreads();
-      if (valid) acc[v] -= xi * (sF[fR] - sF[fL]);
-    }
-    __syncthreads();
   }
-  if (valid) {
-    double* part = partb + NV * G.off;
+  // velocity along the box axis and pressure of every staged cell, kept in
+  // registers by the thread that stages it
+  double cu[3], cp, hu[APT], hp[APT];
+  {
+    cp = aux[qc];
+    const double cc = aux[N + qc];
+    const unsigned char fc = flag[qc];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) part[v * N + q] = acc[v];
+    for (int d = 0; d < 3; ++d) {
+      cu[d] = aux[(4 + d) * N + qc];
+      s_spd[cs[d]] = fabs(cu[d]) + cc;
+      s_p[cs[d]] = cp;
+      s_fl[cs[d]] = fc;
+    }
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      hu[k] = aux[(4 + ax[k]) * N + aq[k]];
+      hp[k] = aux[aq[k]];
+      s_spd[as[k]] = fabs(hu[k]) + aux[N + aq[k]];
+      s_p[as[k]] = hp[k];
+      s_fl[as[k]] = flag[aq[k]];
+    }
+  }
+  __syncthreads();
+  // this thread's faces: stencil start slot, stride along the axis, hybrid
+  // decision and Lax-Friedrichs speed
+  int fe0[XFPT], fst[XFPT];
+  unsigned fte = 0;
+  double fal[XFPT];
+  const unsigned flags = A.flags;
+#pragma unroll
+  for (int k = 0; k < XFPT; ++k) {
+    const int f = t + k * BLK;
+    fe0[k] = -1;
+    fst[k] = 1;
+    fal[k] = 0.0;
+    if (f < Ftot) {
+      const int d = f < foff[1] ? 0 : (f < foff[2] ? 1 : 2);
+      const int r = f - foff[d];
+      const int F0 = T[0] + (d == 0 ? 1 : 0), F1 = T[1] + (d == 1 ? 1 : 0);
+      const int fb[3] = {r % F0, (r / F0) % F1, r / (F0 * F1)};
+      // stencil positions j-3..j+2 of the tile = box positions j..j+5 along d
+      const int e0 = bslot(d, fb[0], fb[1], fb[2]);
+      const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
+      const int bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
+      fe0[k] = e0;
+      fst[k] = bs;
+      bool te;
+      if (flags & HTR_FORCE_TENO) te = true;
+      else if (flags & HTR_FORCE_CENTRAL) te = false;
+      else {
+        int any = 0;
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) any |= s_fl[e0 + mm * bs];
+        const double pa = s_p[e0 + 2 * bs], pb = s_p[e0 + 3 * bs];
+        const double psi = fabs(pb - pa) / fmin(pa, pb);
+        te = any != 0 || psi > psi_c;
+      }
+      if (te) {
+        fte |= 1u << k;
+        double al = s_spd[e0];
+#pragma unroll
+        for (int mm = 1; mm < 6; ++mm) al = fmax(al, s_spd[e0 + mm * bs]);
+        fal[k] = al;
+      }
+    }
+  }
+  // this cell's two faces per axis in the face list, and the metric
+  int fL[3], fR[3];
+  double xi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int lf[3] = {l[0], l[1], l[2]};
+    const int F0 = T[0] + (d == 0 ? 1 : 0), F1 = T[1] + (d == 1 ? 1 : 0);
+    fL[d] = foff[d] + lf[0] + F0 * (lf[1] + F1 * lf[2]);
+    lf[d] += 1;
+    fR[d] = foff[d] + lf[0] + F0 * (lf[1] + F1 * lf[2]);
+    xi[d] = (valid && act[d]) ? G.xin[d][gc[d]] : 0.0;
+  }
+  const long long q = valid ? qc : 0;
+  // software pipeline: the next variable's staging loads (and source) are in
+  // flight while the current variable's faces are evaluated
+  double ncore = U[qc], narm[APT];
+#pragma unroll
+  for (int k = 0; k < APT; ++k) narm[k] = U[aq[k]];
+  double nsrc = valid ? src[q] : 0.0;
+  double* part = partb + NV * G.off;
+  __syncthreads();   // the decisions have read the node speeds, pressures and flags
+#pragma unroll 1
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      s_U[cs[d]] = ncore;
+      s_Fn[cs[d]] = node_flux<NS>(v, d, ncore, cu[d], cp);
+    }
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+      s_U[as[k]] = narm[k];
+      s_Fn[as[k]] = node_flux<NS>(v, ax[k], narm[k], hu[k], hp[k]);
+    }
+    const double acc0 = nsrc;
+    if (v + 1 < NV) {
+      ncore = U[(v + 1) * N + qc];
+#pragma unroll
+      for (int k = 0; k < APT; ++k) narm[k] = U[(v + 1) * N + aq[k]];
+      const int sv = v + 1 < NS ? v + 1 : (v + 1 == NS + 3 ? NS : -1);
+      nsrc = (valid && sv >= 0) ? src[sv * N + q] : 0.0;
+    }
+    __syncthreads();
+    double* sF = s_F[v & 1];
+#pragma unroll
+    for (int k = 0; k < XFPT; ++k) {
+      if (fe0[k] < 0) continue;
+      const int e0 = fe0[k], bs = fst[k];
+      double f6[6];
+#pragma unroll
+      for (int mm = 0; mm < 6; ++mm) f6[mm] = s_Fn[e0 + mm * bs];
+      double Fh;
+      if (!((fte >> k) & 1u)) {
+        // the face value goes through LDS before it is differenced, so its
+        // last rounding cannot be fused into the difference
+        Fh = (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
+      } else {
+        double u6[6];
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) u6[mm] = s_U[e0 + mm * bs];
+        Fh = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4], u6[5],
+                       fal[k], CT);
+      }
+      sF[t + k * BLK] = Fh;
+    }
+    __syncthreads();
+    if (valid) {
+      double acc = acc0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (act[d]) acc -= xi[d] * (sF[fR[d]] - sF[fL[d]]);
+      part[v * N + q] = acc;
+    }
   }
 }
 
