@@ -171,6 +171,7 @@ def ensemble_measure(steps, warm=1, sizes=None):
     z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")  # noqa: E731
     t, dt, J = z(b.nmem), z(b.nmem), z(b.nmem)
     work = b.new_work()
+    shapes, grid = htr.htr_batch_autotune(b, U, T.clone(), work)
     stream = torch.cuda.current_stream()
     htr.htr_rk3_steps_batched(b, U, T, t, dt, 1, steps, work, J, use_graph=True)   # capture + warm-up
     torch.cuda.synchronize()
@@ -187,6 +188,7 @@ def ensemble_measure(steps, warm=1, sizes=None):
     mems = []
     for m, c in enumerate(e.members):
         g = htr.Context(e.mech, c.grid)
+        htr.htr_set_tiling(g, shapes[m], 0)     # the shape tuned for its size class
         mems.append((g, htr.cons_from_case(g, c), htr.to_dev(c.T), z(1), z(1), z(1), g.new_work(),
                      htr.to_dev(e.dlnA[m]), c.laser))
 
@@ -208,7 +210,9 @@ def ensemble_measure(steps, warm=1, sizes=None):
                         f"{{{','.join(map(str, Ns))}}}, {b.N} cells, {steps} RK3 steps", "cells": b.N, "steps": steps,
             "batched_value": cs / t_b, "per_member_value": cs / t_m, "unit": "cell-stage updates/s",
             "batched_over_per_member": t_m / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
-            "per_member_ms_per_step": 1e3 * t_m / steps}
+            "per_member_ms_per_step": 1e3 * t_m / steps,
+            "tiles": {f"{n}^3": "x".join(map(str, shapes[[int(round(c.grid.N ** (1 / 3))) for c in e.members].index(n)]))
+                      for n in Ns}, "persistent_grid": grid}
 
 
 def adjoint_measure(nsteps=50, every=10, n=64):
@@ -226,6 +230,7 @@ def adjoint_measure(nsteps=50, every=10, n=64):
     U0 = htr.cons_from_case(ctx, case)
     T0 = htr.to_dev(case.T)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    htr.htr_autotune(ctx, U0, T0.clone(), ctx.new_work())
     htr.htr_stable_dt(ctx, U0, T0.clone(), dt)
     prob = HeatReleaseProblem(ctx, U0, T0, case.laser, float(dt.item()), nsteps, checkpoint_every=every)
     theta = torch.tensor([case.laser.E, *case.laser.center] + [0.0] * case.mech.nr, dtype=torch.float64,
@@ -258,6 +263,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles (no autotuning)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -280,6 +286,7 @@ def main():
     J_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     work = ctx.new_work()
     laser = case.laser if case.laser.on else None
+    tile, grid = htr.htr_autotune(ctx, U, T.clone(), work) if not args.no_autotune else htr.htr_get_tiling(ctx)
 
     def step():
         htr.htr_rk3_step(ctx, U, T, t_dev, dt_dev, 1, laser, None, work, J_dev)
@@ -350,7 +357,8 @@ def main():
                                "Mach 0.3, SSP-RK3 with in-step CFL dt"
                    if args.workload == "tgv128" else
                    "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser",
-                   "cells": N, "species": ns, "reactions": nr, "stages_per_step": 3},
+                   "cells": N, "species": ns, "reactions": nr, "stages_per_step": 3,
+                   "tile": "x".join(map(str, tile)), "persistent_grid": grid},
         "roofline": roof,
     }
     if args.ens_steps > 0:

@@ -278,6 +278,39 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
 /* As htr_check, for the ensemble's status word. */
 htr_status htr_batch_check(htr_batch* b, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Tiles, persistent launches, autotuning.  The flux sweeps work on 256-cell
+ * tiles; any shape with extent 1 along inactive axes that their staging
+ * buffers hold is accepted (16x4x4, 8x8x4, 8x4x8, 4x8x8 in 3-D; 16x16,
+ * 32x8, 8x32, 64x4 in 2-D; 256 in 1-D).  grid > 0 launches the forward
+ * kernels (per-cell, sensor, both sweeps) as grid persistent blocks that
+ * stride over their logical blocks; grid = 0 launches one block per
+ * logical block.  Results are bitwise independent of both choices (every
+ * face is evaluated once with the same arithmetic).  Changing the tiling
+ * synchronises the device, and it discards an ensemble's captured graph.
+ * ------------------------------------------------------------------------ */
+/* HTR_OK if shape[3] is a valid tile for a grid of n[3] cells, else
+ * HTR_EINVAL with the reason in htr_last_error.  Host only. */
+htr_status htr_tile_shape_check(const int32_t n[3], const int32_t shape[3]);
+/* Sets the tile shape (HOST [3]; NULL: the default) and persistent grid. */
+htr_status htr_set_tiling(htr_ctx* ctx, const int32_t shape[3], int32_t grid);
+htr_status htr_get_tiling(const htr_ctx* ctx, int32_t shape[3], int32_t* grid);
+/* Times one RK3 stage (right-hand side and stage update, written to work,
+ * >= htr_work_bytes) for every candidate shape and persistent grid, twice,
+ * and keeps the fastest; writes the choice to shape_out[3] and grid_out
+ * (both nullable).  U and T_io as for htr_rhs (T_io is refreshed); U is not
+ * modified. */
+htr_status htr_autotune(htr_ctx* ctx, const double* U, double* T_io, double* work, void* stream,
+                        int32_t shape_out[3], int32_t* grid_out);
+/* Ensemble: the shape of member m (m = -1: all members; shape NULL: their
+ * defaults) and the batch's persistent grid. */
+htr_status htr_batch_set_tiling(htr_batch* b, int32_t member, const int32_t shape[3], int32_t grid);
+htr_status htr_batch_get_tiling(const htr_batch* b, int32_t member, int32_t shape[3], int32_t* grid);
+/* Tunes the shape of each class of equal-size members (timed on a member
+ * table holding only that class), then the batch's persistent grid; work
+ * >= htr_batch_work_bytes.  Allocates and frees one small device table. */
+htr_status htr_batch_autotune(htr_batch* b, const double* U, double* T_io, double* work, void* stream);
+
 /* Synchronises `stream`, returns the first device-side error latched since
  * the last htr_check (and clears it), or HTR_EDEVICE for a HIP error. */
 htr_status htr_check(htr_ctx* ctx, void* stream);

@@ -90,6 +90,13 @@ def load():
         "htr_batch_work_bytes": (C.c_size_t, [vp]),
         "htr_rk3_steps_batched": (st, [vp, vp, vp, vp, vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
         "htr_batch_check": (st, [vp, vp]),
+        "htr_tile_shape_check": (st, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "htr_set_tiling": (st, [vp, C.POINTER(C.c_int32), C.c_int32]),
+        "htr_get_tiling": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "htr_autotune": (st, [vp, vp, vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "htr_batch_set_tiling": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
+        "htr_batch_get_tiling": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "htr_batch_autotune": (st, [vp, vp, vp, vp, vp]),
         "htr_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -253,8 +253,6 @@ __device__ __forceinline__ void adj_diff_tangential(const Member& G, const int c
 // pattern once (four bits per side, in LDS).  Each node then gathers from
 // the six faces containing it: the face cotangent times the frozen linear
 // coefficient of its stencil position.
-constexpr int EXTA = 896;     // tile extended by 5 + 5 along one axis
-constexpr int FACEA = 640;    // faces touching a tile along one axis
 constexpr int STGA = (EXTA + BLK - 1) / BLK;
 constexpr int FPTA = (FACEA + BLK - 1) / BLK;
 

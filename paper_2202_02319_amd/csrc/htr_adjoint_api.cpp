@@ -50,9 +50,9 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
   a.laser = make_laser(laser, c->n, c->L);
   a.dlnA = dlnA;
   a.flags = c->scheme.flags;
-  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
+  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
                       c->ws.status, 0, st));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, nullptr,
+  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, nullptr,
                        st));
   const int nth = 4 + c->nr;
   HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, T, c->ws.aux, c->ws.flag, lam, s, h, b.ubd, b.pb,

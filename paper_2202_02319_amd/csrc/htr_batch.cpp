@@ -15,28 +15,7 @@
 
 using namespace htr;
 
-struct htr_batch {
-  htr_ctx* ctx = nullptr;
-  int nmem = 0;
-  std::vector<Member> host;
-  std::vector<long long> offs;   // nmem + 1
-  Member* dmem = nullptr;
-  double* dgrid = nullptr;
-  double* ddlnA = nullptr;
-  long long Ntot = 0;
-  int nblocks = 0;
-  int ntblocks = 0;
-  Workspace ws;
-  Timer timer;
-  hipStream_t gstream = nullptr;   // capture/replay stream (default priority)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  const void* key[7] = {};
-  int key_steps = -1, key_cdt = -1;
-};
-
-static Ctx bview(const htr_batch* b) {
+Ctx htr::bview(const htr_batch* b) {
   Ctx v{};
   v.ns = b->ctx->ns;
   v.M = b->ctx->dM;
@@ -44,13 +23,14 @@ static Ctx bview(const htr_batch* b) {
   v.nmem = b->nmem;
   v.nblocks = b->nblocks;
   v.ntblocks = b->ntblocks;
+  v.grid = b->grid;
   v.scheme = b->ctx->scheme;
   v.total_cells = b->Ntot;
   v.timer = const_cast<Timer*>(&b->timer);
   return v;
 }
 
-static void drop_graph(htr_batch* b) {
+void htr::drop_graph(htr_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   b->exec = nullptr;
@@ -98,7 +78,7 @@ htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* m
       M.n[a] = d.n[a];
       M.act[a] = d.n[a] > 1;
     }
-    set_tiles(M, &b->ntblocks);
+    set_tiles(M, nullptr, &b->ntblocks);
     b->offs[m] = off;
     off += N;
     blocks += M.nblocks;

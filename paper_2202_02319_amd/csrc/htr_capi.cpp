@@ -240,7 +240,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   const bool need_red = J_dev != nullptr || want_dt;
   {
     TimedLaunch tl(C.timer, TC_POINT, s);
-    HIP_OK(launch_point(C.ns, C.M, C.mem, C.nmem, C.nblocks, a, U, T, w.aux, w.src, hrr,
+    HIP_OK(launch_point(C.ns, C.M, C.mem, C.nmem, C.nblocks, C.grid, a, U, T, w.aux, w.src, hrr,
                         need_red ? w.blkred : nullptr, nullptr, w.status, want_dt, s));
   }
   if (need_red) {
@@ -249,16 +249,19 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   }
   {
     TimedLaunch tl(C.timer, TC_SENSOR, s);
-    HIP_OK(launch_sensor(C.mem, C.nmem, C.nblocks, w.aux, C.ns, w.flag, w.grad, C.scheme.theta_c, nullptr, s));
+    HIP_OK(launch_sensor(C.mem, C.nmem, C.nblocks, C.grid, w.aux, C.ns, w.flag, w.grad, C.scheme.theta_c, nullptr,
+                         s));
   }
   {
     TimedLaunch tl(C.timer, TC_CONV, s);
-    HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, w.aux, w.src, w.flag, w.part, C.scheme.psi_c,
+    HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, w.aux, w.src, w.flag, w.part,
+                       C.scheme.psi_c,
                        C.scheme.teno_CT, s));
   }
   {
     TimedLaunch tl(C.timer, TC_DIFF, s);
-    HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ntblocks, a, U, Un, T, w.aux, w.grad, w.part, out, ca, cb,
+    HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, Un, T, w.aux, w.grad, w.part, out, ca,
+                       cb,
                        rhs_only, s));
   }
   return HTR_OK;
@@ -296,7 +299,7 @@ htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t
 
 }  // namespace htr
 
-static Ctx view(const htr_ctx* c) {
+Ctx htr::view(const htr_ctx* c) {
   Ctx v{};
   v.ns = c->ns;
   v.M = c->dM;
@@ -304,6 +307,7 @@ static Ctx view(const htr_ctx* c) {
   v.nmem = 1;
   v.nblocks = c->nblocks;
   v.ntblocks = c->ntblocks;
+  v.grid = c->grid;
   v.scheme = c->scheme;
   v.total_cells = c->N;
   for (int a = 0; a < 3; ++a) {
@@ -393,7 +397,7 @@ htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, cons
   M.off = 0;
   M.block_begin = 0;
   M.nblocks = c->nblocks;
-  set_tiles(M, &c->ntblocks);
+  set_tiles(M, nullptr, &c->ntblocks);
   M.laser.on = 0;
   M.dlnA = nullptr;
   if ((e = hipMalloc(&c->dmem, sizeof(Member))) != hipSuccess)
@@ -464,9 +468,9 @@ htr_status htr_cells(htr_ctx* c, const double* U, double* T_io, double t, const 
   a.laser = make_laser(laser, C.n1, C.L1);
   a.flags = c->scheme.flags;
   hipStream_t s = (hipStream_t)stream;
-  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T_io, c->ws.aux, c->ws.src, nullptr, nullptr, out,
+  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T_io, c->ws.aux, c->ws.src, nullptr, nullptr, out,
                       c->ws.status, 0, s));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, out, s));
+  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, out, s));
   return HTR_OK;
 }
 
@@ -477,7 +481,7 @@ htr_status htr_stable_dt(htr_ctx* c, const double* U, double* T_io, double* dt_d
   CallArgs a{};
   a.flags = c->scheme.flags | HTR_CHEM_OFF;   // the step limit needs no chemistry
   hipStream_t s = (hipStream_t)stream;
-  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, a, U, T_io, c->ws.aux, c->ws.src, nullptr, c->ws.blkred,
+  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T_io, c->ws.aux, c->ws.src, nullptr, c->ws.blkred,
                       nullptr, c->ws.status, 1, s));
   HIP_OK(launch_finalize(C.mem, 1, c->ws.blkred, c->scheme.cfl, dt_dev, nullptr, nullptr, 0.0, 1, s));
   return HTR_OK;

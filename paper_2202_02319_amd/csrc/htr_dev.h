@@ -136,6 +136,15 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Staging limits of the tiled kernels; a tile shape is accepted only if it
+// fits all of them (tile_shape_ok).
+constexpr int BLKF = 320;        // threads of the diffusive sweep: one face per thread along an axis
+constexpr int XBOX_MAX = 2208;   // convective cross staging: the three direction boxes (22*4*4 + 16*10*4 + 16*4*10)
+constexpr int XARM_MAX = 864;    // its halo cells: 6 per line along every axis
+constexpr int XFACE_MAX = 912;   // faces over all axes (17*4*4 + 16*5*4 + 16*4*5)
+constexpr int EXTA = 896;        // convective adjoint: tile extended by 5 + 5 along one axis
+constexpr int FACEA = 640;       // faces touching a tile along one axis
+
 // Dispatch on the species count (the kernels are templated on it).
 #define HTR_NS_SWITCH(ns, CALL)                                                        \
   switch (ns) {                                                                        \
@@ -151,19 +160,28 @@ struct Workspace;
 hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
                                const double* Y, const double* T, const double* p, const double* vel, double* U,
                                hipStream_t s);
-hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
+hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
+                        const CallArgs& a,
                         const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
                         double* cells_out, unsigned* status, int want_dt, hipStream_t s);
-hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
+hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, const double* aux, int ns,
+                         unsigned char* flag,
                          double* grad, double theta_c, double* theta_out, hipStream_t s);
-hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
+                       const CallArgs& a,
                        const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
                        double psi_c, double CT, hipStream_t s);
-hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
+                       const CallArgs& a,
                        const double* U, const double* Un, const double* T, const double* aux, const double* grad,
                        const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s);
-// tile shape and tiled-block count of a member (host side)
-void set_tiles(Member& M, int* tblocks);
+// Tile shape of member M (shape == nullptr: the default for its active
+// axes); appends its tiles to the running count *tblocks.
+void set_tiles(Member& M, const int* shape, int* tblocks);
+// Whether a tile shape suits a member with active axes act (message on failure).
+bool tile_shape_ok(const int act[3], const int shape[3], const char** why);
+// Default tile shape for the active axes.
+void default_tile_shape(const int act[3], int shape[3]);
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);

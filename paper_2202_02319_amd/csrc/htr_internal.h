@@ -65,6 +65,7 @@ struct Ctx {
   int nmem = 1;
   int nblocks = 0;
   int ntblocks = 0;               // tiled launches
+  int grid = 0;                   // persistent grid of the forward kernels (0: one block per logical block)
   htr_scheme scheme{};
   long long total_cells = 0;
   int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
@@ -99,6 +100,37 @@ struct htr_ctx {
   long long N = 0;
   int nblocks = 0;
   int ntblocks = 0;
+  int grid = 0;                    // persistent grid (0: off)
   htr::Workspace ws;
   htr::Timer timer;
 };
+
+// An ensemble (the opaque htr_batch of the C interface).
+struct htr_batch {
+  htr_ctx* ctx = nullptr;
+  int nmem = 0;
+  std::vector<htr::Member> host;
+  std::vector<long long> offs;   // nmem + 1
+  htr::Member* dmem = nullptr;
+  double* dgrid = nullptr;
+  double* ddlnA = nullptr;
+  long long Ntot = 0;
+  int nblocks = 0;
+  int ntblocks = 0;
+  int grid = 0;                    // persistent grid (0: off)
+  htr::Workspace ws;
+  htr::Timer timer;
+  hipStream_t gstream = nullptr;   // capture/replay stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[7] = {};
+  int key_steps = -1, key_cdt = -1;
+};
+
+
+namespace htr {
+Ctx view(const htr_ctx* c);
+Ctx bview(const htr_batch* b);
+void drop_graph(htr_batch* b);   // the captured graph no longer matches the member table
+}  // namespace htr

@@ -92,20 +92,22 @@ __global__ __launch_bounds__(BLK) void k_prim_to_cons(const MechTables* __restri
 // ------------------------------------------------------------------ point
 // aux rows per cell: 0 p, 1 c, 2 mu, 3 lambda, 4..6 velocity, 7.. D_s.
 // src rows: 0..NS-1 wdot_s, NS q_L.  blkred per block: {sum dV hrr, min dt limit}.
+// One logical block bl of 256 cells.
 template <int NS>
-__global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
-                                               int nmem, CallArgs A, const double* __restrict__ Ub,
-                                               double* __restrict__ Tb, double* __restrict__ auxb,
-                                               double* __restrict__ srcb, double* __restrict__ hrrb,
-                                               double* __restrict__ blkred, double* __restrict__ cellsb,
-                                               unsigned* __restrict__ status, int want_dt) {
+__device__ __forceinline__ void point_block(int bl, const MechTables* __restrict__ M,
+                                            const Member* __restrict__ mem, int nmem, const CallArgs& A,
+                                            const double* __restrict__ Ub, double* __restrict__ Tb,
+                                            double* __restrict__ auxb, double* __restrict__ srcb,
+                                            double* __restrict__ hrrb, double* __restrict__ blkred,
+                                            double* __restrict__ cellsb, unsigned* __restrict__ status,
+                                            int want_dt) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   __shared__ double conc[NS][BLK];
   __shared__ double wred[2][BLK / 64];
-  const int m = find_member(mem, nmem, blockIdx.x);
+  const int m = find_member(mem, nmem, bl);
   const Member& G = mem[m];
   const int tid = threadIdx.x;
-  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + tid;
+  const long long q = (long long)(bl - G.block_begin) * BLK + tid;
   const bool live = q < G.N;
   const long long N = G.N;
   const unsigned flags = A.flags;
@@ -353,9 +355,30 @@ __global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables
         sh += wred[0][k];
         sl = fmin(sl, wred[1][k]);
       }
-      blkred[2 * blockIdx.x] = sh;
-      blkred[2 * blockIdx.x + 1] = sl;
+      blkred[2 * bl] = sh;
+      blkred[2 * bl + 1] = sl;
     }
+  }
+}
+
+// Grid-stride over the nlog logical blocks: one pass when the grid has one
+// block per logical block, persistent blocks when it has fewer.
+template <int NS, bool PERSIST>
+__global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables* __restrict__ M,
+                                                                const Member* __restrict__ mem, int nmem, int nlog,
+                                                                CallArgs A, const double* __restrict__ Ub,
+                                                                double* __restrict__ Tb, double* __restrict__ auxb,
+                                                                double* __restrict__ srcb, double* __restrict__ hrrb,
+                                                                double* __restrict__ blkred,
+                                                                double* __restrict__ cellsb,
+                                                                unsigned* __restrict__ status, int want_dt) {
+  if (!PERSIST) {
+    point_block<NS>(blockIdx.x, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt);
+    return;
+  }
+  for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
+    point_block<NS>(bl, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt);
+    __syncthreads();   // the next logical block reuses the LDS
   }
 }
 
@@ -363,13 +386,13 @@ __global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables
 // theta = (div u)^2 / ((div u)^2 + |curl u|^2 + 1e-300) with second-order
 // central differences; flag = theta > theta_c.  Also stores the nodal
 // velocity gradient (the tangential derivatives of the diffusive fluxes).
-__global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, int nmem,
-                                                const double* __restrict__ auxb, int naux,
-                                                unsigned char* __restrict__ flagb, double* __restrict__ gradb,
-                                                double theta_c, double* __restrict__ theta_out, int nq) {
-  const int m = find_member(mem, nmem, blockIdx.x);
+__device__ __forceinline__ void sensor_block(int bl, const Member* __restrict__ mem, int nmem,
+                                             const double* __restrict__ auxb, int naux,
+                                             unsigned char* __restrict__ flagb, double* __restrict__ gradb,
+                                             double theta_c, double* __restrict__ theta_out, int nq) {
+  const int m = find_member(mem, nmem, bl);
   const Member& G = mem[m];
-  const long long q = (long long)(blockIdx.x - G.block_begin) * BLK + threadIdx.x;
+  const long long q = (long long)(bl - G.block_begin) * BLK + threadIdx.x;
   if (q >= G.N) return;
   const long long N = G.N;
   const double* vel = auxb + naux * G.off + 4 * N;
@@ -400,6 +423,19 @@ __global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, 
   const double th = d2 / (d2 + wx * wx + wy * wy + wz * wz + 1e-300);
   flagb[G.off + q] = th > theta_c ? 1 : 0;
   if (theta_out) theta_out[(nq - 1) * N + nq * G.off + q] = th;
+}
+
+template <bool PERSIST>
+__global__ __launch_bounds__(BLK) void k_sensor(const Member* __restrict__ mem, int nmem, int nlog,
+                                                const double* __restrict__ auxb, int naux,
+                                                unsigned char* __restrict__ flagb, double* __restrict__ gradb,
+                                                double theta_c, double* __restrict__ theta_out, int nq) {
+  if (!PERSIST) {
+    sensor_block(blockIdx.x, mem, nmem, auxb, naux, flagb, gradb, theta_c, theta_out, nq);
+    return;
+  }
+  for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x)
+    sensor_block(bl, mem, nmem, auxb, naux, flagb, gradb, theta_c, theta_out, nq);
 }
 
 // ------------------------------------------------------------- reductions
@@ -451,13 +487,20 @@ static hipError_t prim_to_cons_t(const MechTables* M, const Member* mem, int nme
 }
 
 template <int NS>
-static hipError_t point_t(const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
-                          const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
-                          double* cells, unsigned* status, int want_dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_point<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, T, aux, src, hrr, blkred,
-                     cells, status, want_dt);
+static hipError_t point_t(const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
+                          const CallArgs& a, const double* U, double* T, double* aux, double* src, double* hrr,
+                          double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s) {
+  if (grid < nblocks)
+    hipLaunchKernelGGL((k_point<NS, true>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux, src,
+                       hrr, blkred, cells, status, want_dt);
+  else
+    hipLaunchKernelGGL((k_point<NS, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux, src,
+                       hrr, blkred, cells, status, want_dt);
   return hipGetLastError();
 }
+
+// grid <= 0 or >= nblocks: one block per logical block
+static int grid_of(int nblocks, int grid) { return (grid <= 0 || grid > nblocks) ? nblocks : grid; }
 
 hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
                                const double* Y, const double* T, const double* p, const double* vel, double* U,
@@ -467,18 +510,24 @@ hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, i
 #undef C_
 }
 
-hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, const CallArgs& a,
-                        const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
-                        double* cells, unsigned* status, int want_dt, hipStream_t s) {
-#define C_(NS) point_t<NS>(M, mem, nmem, nblocks, a, U, T, aux, src, hrr, blkred, cells, status, want_dt, s)
+hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
+                        const CallArgs& a, const double* U, double* T, double* aux, double* src, double* hrr,
+                        double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s) {
+  grid = grid_of(nblocks, grid);
+#define C_(NS) point_t<NS>(M, mem, nmem, nblocks, grid, a, U, T, aux, src, hrr, blkred, cells, status, want_dt, s)
   HTR_NS_SWITCH(ns, C_)
 #undef C_
 }
 
-hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, const double* aux, int ns, unsigned char* flag,
-                         double* grad, double theta_c, double* theta_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, nmem, aux, 7 + ns, flag, grad, theta_c,
-                     theta_out, 5 + 2 * ns + 3);
+hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, const double* aux, int ns,
+                         unsigned char* flag, double* grad, double theta_c, double* theta_out, hipStream_t s) {
+  grid = grid_of(nblocks, grid);
+  if (grid < nblocks)
+    hipLaunchKernelGGL(k_sensor<true>, dim3(grid), dim3(BLK), 0, s, mem, nmem, nblocks, aux, 7 + ns, flag, grad,
+                       theta_c, theta_out, 5 + 2 * ns + 3);
+  else
+    hipLaunchKernelGGL(k_sensor<false>, dim3(grid), dim3(BLK), 0, s, mem, nmem, nblocks, aux, 7 + ns, flag, grad,
+                       theta_c, theta_out, 5 + 2 * ns + 3);
   return hipGetLastError();
 }
 

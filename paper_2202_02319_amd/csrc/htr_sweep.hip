@@ -21,12 +21,12 @@
 namespace htr {
 
 
-// Tile shape of the tiled kernels: 256 cells, 16 x 4 x 4 on 3-D grids,
-// 16 x 16 over the two active axes of 2-D grids, 256 along a 1-D grid.
-void set_tiles(Member& M, int* tblocks) {
-  int act[3] = {M.act[0], M.act[1], M.act[2]};
+// Tile shapes of the tiled kernels: 256 cells.  Default 16 x 4 x 4 on 3-D
+// grids, 16 x 16 over the two active axes of 2-D grids, 256 along a 1-D
+// grid; other shapes are accepted if every staging buffer holds them.
+void default_tile_shape(const int act[3], int t[3]) {
   const int na = act[0] + act[1] + act[2];
-  int t[3] = {1, 1, 1};
+  t[0] = t[1] = t[2] = 1;
   if (na == 3) {
     t[0] = 16; t[1] = 4; t[2] = 4;
   } else if (na == 2) {
@@ -35,6 +35,41 @@ void set_tiles(Member& M, int* tblocks) {
     for (int a = 0; a < 3; ++a) t[a] = act[a] ? 256 : 1;
   } else {
     t[0] = 256;
+  }
+}
+
+bool tile_shape_ok(const int act[3], const int t[3], const char** why) {
+  const char* w = nullptr;
+  const int na = act[0] + act[1] + act[2];
+  if (t[0] < 1 || t[1] < 1 || t[2] < 1 || t[0] * t[1] * t[2] != BLK) w = "tile must have 256 cells";
+  for (int a = 0; a < 3 && !w; ++a)
+    if (na > 0 && !act[a] && t[a] != 1) w = "tile extends along an inactive axis";
+  if (!w) {
+    long box = 0, arms = 0, faces = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (!act[d]) continue;
+      const long cs = BLK / t[d];   // cross-section of the tile normal to d
+      box += cs * (t[d] + 6);
+      arms += 6 * cs;
+      faces += cs * (t[d] + 1);
+      if (!w && cs * (t[d] + 1) > BLKF) w = "too many faces along one axis for the diffusive sweep";
+      if (!w && (cs * (t[d] + 10) > EXTA || cs * (t[d] + 5) > FACEA))
+        w = "halo box too large for the convective adjoint";
+    }
+    if (!w && (box > XBOX_MAX || arms > XARM_MAX || faces > XFACE_MAX))
+      w = "cross staging too large for the convective sweep";
+  }
+  if (why) *why = w;
+  return w == nullptr;
+}
+
+void set_tiles(Member& M, const int* shape, int* tblocks) {
+  const int act[3] = {M.act[0], M.act[1], M.act[2]};
+  int t[3];
+  if (shape) {
+    t[0] = shape[0]; t[1] = shape[1]; t[2] = shape[2];
+  } else {
+    default_tile_shape(act, t);
   }
   int nb = 1;
   for (int a = 0; a < 3; ++a) {
@@ -62,7 +97,6 @@ __device__ __attribute__((noinline)) double teno_face(double f0, double f1, doub
   return teno6(fp, CT) + teno6(fm, CT);
 }
 
-constexpr int BLKF = 320;        // threads of the diffusive sweep: one per face of a tile along an axis
 
 __device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
   return ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
@@ -72,9 +106,6 @@ __device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
 // sides along every active axis.  Each staged value is loaded once and
 // written into the line-contiguous box of every direction that uses it (the
 // tile's own cells into all of them).
-constexpr int XBOX_MAX = 2208;   // three direction boxes of a 16x4x4 tile: 22*4*4 + 16*10*4 + 16*4*10
-constexpr int XARM_MAX = 864;    // halo cells: 6 per line along every axis
-constexpr int XFACE_MAX = 912;   // faces over all axes: 17*4*4 + 16*5*4 + 16*4*5
 constexpr int APT = (XARM_MAX + BLK - 1) / BLK;
 constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
 
@@ -87,11 +118,10 @@ constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
 // in registers), and every face flux is evaluated once from them, all
 // directions together.
 template <int NS>
-__global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
-                                              int nmem, CallArgs A, const double* __restrict__ Ub,
-                                              const double* __restrict__ auxb, const double* __restrict__ srcb,
-                                              const unsigned char* __restrict__ flagb, double* __restrict__ partb,
-                                              double psi_c, double CT) {
+__device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem, int nmem, const CallArgs& A,
+                                          const double* __restrict__ Ub, const double* __restrict__ auxb,
+                                          const double* __restrict__ srcb, const unsigned char* __restrict__ flagb,
+                                          double* __restrict__ partb, double psi_c, double CT) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
@@ -100,11 +130,11 @@ __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ 
   double* s_spd = s_U;
   double* s_p = s_Fn;
   unsigned char* s_fl = reinterpret_cast<unsigned char*>(&s_F[0][0]);
-  const int m = find_member_tiled(mem, nmem, blockIdx.x);
+  const int m = find_member_tiled(mem, nmem, bl);
   const Member& G = mem[m];
   const int t = threadIdx.x;
   int o[3];
-  tile_origin(G, blockIdx.x - G.tblock_begin, o);
+  tile_origin(G, bl - G.tblock_begin, o);
   const int T[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
   const int TT = T[0] * T[1] * T[2];
   const bool act[3] = {G.act[0] != 0, G.act[1] != 0, G.act[2] != 0};
@@ -324,6 +354,24 @@ __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ 
   }
 }
 
+// Grid-stride over the nlog tiles: one pass when the grid has one block per
+// tile, persistent blocks when it has fewer.
+template <int NS, bool PERSIST>
+__global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                              int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
+                                              const double* __restrict__ auxb, const double* __restrict__ srcb,
+                                              const unsigned char* __restrict__ flagb, double* __restrict__ partb,
+                                              double psi_c, double CT) {
+  if (!PERSIST) {
+    conv_tile<NS>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, psi_c, CT);
+    return;
+  }
+  for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
+    conv_tile<NS>(bl, mem, nmem, A, Ub, auxb, srcb, flagb, partb, psi_c, CT);
+    __syncthreads();   // the next tile reuses the LDS
+  }
+}
+
 // Diffusive flux at the face between nodes qA and qB = A + e_d, in the sign
 // with which it enters the right-hand side.  Tangential velocity derivatives
 // at the face are the mean of the nodal central differences (grad).  Every
@@ -467,20 +515,19 @@ __device__ __forceinline__ void diff_dir(const MechTables* __restrict__ M, const
 // BLKF threads: the first BLK own the tile's cells; every thread owns one
 // face per direction (a tile has at most BLKF faces along any axis).
 template <int NS>
-__global__ __launch_bounds__(BLKF, 3) void k_diff(const MechTables* __restrict__ M,
-                                                       const Member* __restrict__ mem, int nmem, CallArgs A,
-                                                       const double* __restrict__ Ub, const double* Unb,
-                                                       const double* __restrict__ Tb, const double* __restrict__ auxb,
-                                                       const double* __restrict__ gradb,
-                                                       const double* __restrict__ partb, double* outb, double ca,
-                                                       double cb, int rhs_only) {
+__device__ __forceinline__ void diff_tile(int bl, const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                          int nmem, const CallArgs& A, const double* __restrict__ Ub,
+                                          const double* Unb, const double* __restrict__ Tb,
+                                          const double* __restrict__ auxb, const double* __restrict__ gradb,
+                                          const double* __restrict__ partb, double* outb, double ca, double cb,
+                                          int rhs_only) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   __shared__ double s_Fd[NV][BLKF];
-  const int m = find_member_tiled(mem, nmem, blockIdx.x);
+  const int m = find_member_tiled(mem, nmem, bl);
   const Member& G = mem[m];
   const int t = threadIdx.x;
   int o[3];
-  tile_origin(G, blockIdx.x - G.tblock_begin, o);
+  tile_origin(G, bl - G.tblock_begin, o);
   const int T0 = G.tdim[0], T1 = G.tdim[1];
   const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
   const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
@@ -528,36 +575,66 @@ __global__ __launch_bounds__(BLKF, 3) void k_diff(const MechTables* __restrict__
   }
 }
 
+template <int NS, bool PERSIST>
+__global__ __launch_bounds__(BLKF, 3) void k_diff(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                  int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
+                                                  const double* Unb, const double* __restrict__ Tb,
+                                                  const double* __restrict__ auxb, const double* __restrict__ gradb,
+                                                  const double* __restrict__ partb, double* outb, double ca,
+                                                  double cb, int rhs_only) {
+  if (!PERSIST) {
+    diff_tile<NS>(blockIdx.x, M, mem, nmem, A, Ub, Unb, Tb, auxb, gradb, partb, outb, ca, cb, rhs_only);
+    return;
+  }
+  for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
+    diff_tile<NS>(bl, M, mem, nmem, A, Ub, Unb, Tb, auxb, gradb, partb, outb, ca, cb, rhs_only);
+    __syncthreads();   // the next tile reuses the LDS
+  }
+}
+
+static int grid_of(int nblocks, int grid) { return (grid <= 0 || grid > nblocks) ? nblocks : grid; }
+
 template <int NS>
-static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid, const CallArgs& a,
                          const double* U, const double* aux, const double* src, const unsigned char* flag,
                          double* part, double psi_c, double CT, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv<NS>, dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part, psi_c,
-                     CT);
+  if (grid < ntblocks)
+    hipLaunchKernelGGL((k_conv<NS, true>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, psi_c, CT);
+  else
+    hipLaunchKernelGGL((k_conv<NS, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, psi_c, CT);
   return hipGetLastError();
 }
 
 template <int NS>
-static hipError_t diff_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
+static hipError_t diff_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid, const CallArgs& a,
                          const double* U, const double* Un, const double* T, const double* aux, const double* grad,
                          const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_diff<NS>, dim3(ntblocks), dim3(BLKF), 0, s, M, mem, nmem, a, U, Un, T, aux, grad, part, out,
-                     ca, cb, rhs_only);
+  if (grid < ntblocks)
+    hipLaunchKernelGGL((k_diff<NS, true>), dim3(grid), dim3(BLKF), 0, s, M, mem, nmem, ntblocks, a, U, Un, T, aux,
+                       grad, part, out, ca, cb, rhs_only);
+  else
+    hipLaunchKernelGGL((k_diff<NS, false>), dim3(grid), dim3(BLKF), 0, s, M, mem, nmem, ntblocks, a, U, Un, T, aux,
+                       grad, part, out, ca, cb, rhs_only);
   return hipGetLastError();
 }
 
-hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
-                       const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
-                       double psi_c, double CT, hipStream_t s) {
-#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, a, U, aux, src, flag, part, psi_c, CT, s)
+hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
+                       const CallArgs& a, const double* U, const double* aux, const double* src,
+                       const unsigned char* flag, double* part, double psi_c, double CT, hipStream_t s) {
+  grid = grid_of(ntblocks, grid);
+#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, grid, a, U, aux, src, flag, part, psi_c, CT, s)
   HTR_NS_SWITCH(ns, C_);
 #undef C_
 }
 
-hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, const CallArgs& a,
-                       const double* U, const double* Un, const double* T, const double* aux, const double* grad,
-                       const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
-#define C_(NS) diff_t<NS>(M, mem, nmem, ntblocks, a, U, Un, T, aux, grad, part, out, ca, cb, rhs_only, s)
+hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
+                       const CallArgs& a, const double* U, const double* Un, const double* T, const double* aux,
+                       const double* grad, const double* part, double* out, double ca, double cb, int rhs_only,
+                       hipStream_t s) {
+  grid = grid_of(ntblocks, grid);
+#define C_(NS) diff_t<NS>(M, mem, nmem, ntblocks, grid, a, U, Un, T, aux, grad, part, out, ca, cb, rhs_only, s)
   HTR_NS_SWITCH(ns, C_);
 #undef C_
 }

@@ -195,6 +195,53 @@ def htr_rk3_step_adjoint(ctx, Un, stages, T_io, t, dt, laser, dlnA_dev, Jbar, Ub
                                        _ptr(pbar_acc), _ptr(adj_work), _stream(stream)))
 
 
+def _i3(v):
+    return (C.c_int32 * 3)(*[int(x) for x in v])
+
+
+def htr_tile_shape_check(n, shape):
+    """Host-only check that shape is a valid tile for a grid of n cells;
+    raises HTRError with the reason otherwise."""
+    check(_lib.load().htr_tile_shape_check(_i3(n), _i3(shape)))
+
+
+def htr_set_tiling(ctx, shape=None, grid=0):
+    check(ctx.lib.htr_set_tiling(ctx.h, _i3(shape) if shape is not None else None, int(grid)))
+
+
+def htr_get_tiling(ctx):
+    """(tile shape, persistent grid) of the context."""
+    sh, g = (C.c_int32 * 3)(), C.c_int32()
+    check(ctx.lib.htr_get_tiling(ctx.h, sh, C.byref(g)))
+    return tuple(sh), g.value
+
+
+def htr_autotune(ctx, U, T_io, work, stream=None):
+    """Times every candidate tile shape and persistent grid on one RHS and
+    keeps the fastest; returns (shape, grid)."""
+    sh, g = (C.c_int32 * 3)(), C.c_int32()
+    check(ctx.lib.htr_autotune(ctx.h, _ptr(U), _ptr(T_io), _ptr(work), _stream(stream), sh, C.byref(g)))
+    return tuple(sh), g.value
+
+
+def htr_batch_set_tiling(b, member=-1, shape=None, grid=0):
+    check(b.lib.htr_batch_set_tiling(b.h, int(member), _i3(shape) if shape is not None else None, int(grid)))
+
+
+def htr_batch_get_tiling(b, member):
+    sh, g = (C.c_int32 * 3)(), C.c_int32()
+    check(b.lib.htr_batch_get_tiling(b.h, int(member), sh, C.byref(g)))
+    return tuple(sh), g.value
+
+
+def htr_batch_autotune(b, U, T_io, work, stream=None):
+    """Tunes each equal-size member class's tile shape, then the persistent
+    grid; returns the per-member shapes and the grid."""
+    check(b.lib.htr_batch_autotune(b.h, _ptr(U), _ptr(T_io), _ptr(work), _stream(stream)))
+    shapes = [htr_batch_get_tiling(b, m)[0] for m in range(b.nmem)]
+    return shapes, htr_batch_get_tiling(b, 0)[1]
+
+
 def htr_check(ctx, stream=None):
     check(ctx.lib.htr_check(ctx.h, _stream(stream)))
 
