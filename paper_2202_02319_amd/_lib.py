@@ -81,7 +81,9 @@ def load():
         "htr_rhs_adjoint": (st, [vp, vp, vp, C.c_double, C.POINTER(htr_laser), vp, vp, C.c_double, C.c_double, vp,
                                  vp, vp, vp]),
         "htr_rk3_step_adjoint": (st, [vp, vp, vp, vp, C.c_double, C.c_double, C.POINTER(htr_laser), vp,
-                                      C.c_double, vp, vp, vp, vp]),
+                                      C.c_double, vp, vp, vp, vp, vp]),
+        "htr_tape_bytes": (C.c_size_t, [vp]),
+        "htr_rk3_step_taped": (st, [vp, vp, vp, vp, vp, C.c_int, C.POINTER(htr_laser), vp, vp, vp, vp, vp]),
         "htr_batch_create": (st, [vp, C.c_int32, C.POINTER(htr_member_desc), C.POINTER(vp)]),
         "htr_batch_destroy": (st, [vp]),
         "htr_batch_cells": (C.c_int64, [vp, C.POINTER(C.c_int64)]),

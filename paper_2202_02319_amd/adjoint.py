@@ -5,8 +5,9 @@ J(theta) = sum_steps dt sum_k b_k sum_cells dV HRR(U^(k), t_k) for a fixed
 number of SSP-RK3 steps with a frozen step dt, theta = (E, centre x, y, z,
 ln A offsets of every reaction).  The forward pass keeps the state every
 `checkpoint_every` steps; the backward pass re-runs each segment keeping its
-stage states and walks it in reverse with htr_rk3_step_adjoint.  All
-arithmetic runs in the HIP library; torch holds the buffers.
+stage states and forward tapes and walks it in reverse with
+htr_rk3_step_adjoint.  All arithmetic runs in the HIP library; torch holds
+the buffers.
 """
 from __future__ import annotations
 
@@ -27,6 +28,10 @@ class HeatReleaseProblem:
         self.work = ctx.new_work()
         self.adj_work = htr.new_adjoint_work(ctx)
         self.nth = 4 + ctx.nr
+        # one segment's re-run: per step its start state, stage states and forward tape
+        self.seg_states = [torch.empty_like(self.U0) for _ in range(self.K)]
+        self.seg_stages = [torch.empty_like(self.work) for _ in range(self.K)]
+        self.seg_tapes = [htr.new_tape(ctx) for _ in range(self.K)]
 
     def _laser_for(self, theta):
         L = copy.copy(self.laser)
@@ -35,10 +40,13 @@ class HeatReleaseProblem:
         L.center = (th[1], th[2], th[3])
         return L
 
-    def _step(self, U, T, t, L, dlnA, J):
+    def _step(self, U, T, t, L, dlnA, J, work=None, tape=None):
         t_dev = torch.full((1,), t, dtype=torch.float64, device=U.device)
         dt_dev = torch.full((1,), self.dt, dtype=torch.float64, device=U.device)
-        htr.htr_rk3_step(self.ctx, U, T, t_dev, dt_dev, 0, L, dlnA, self.work, J)
+        if tape is None:
+            htr.htr_rk3_step(self.ctx, U, T, t_dev, dt_dev, 0, L, dlnA, self.work, J)
+        else:
+            htr.htr_rk3_step_taped(self.ctx, U, T, t_dev, dt_dev, 0, L, dlnA, work, J, tape)
 
     def forward(self, theta):
         """J and the checkpoints [(step, U, T)]."""
@@ -64,17 +72,15 @@ class HeatReleaseProblem:
         for (n0, Uc, Tc) in reversed(ckpts):
             n1 = min(n0 + self.K, self.nsteps)
             U, T = Uc.clone(), Tc.clone()
-            states, stages, temps = [], [], []
-            for n in range(n0, n1):
-                states.append(U.clone())
-                temps.append(T.clone())
-                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J)
-                stages.append(self.work.clone())
+            # re-run the segment, keeping each step's start state, stage
+            # states and tape (per-cell fields, T and sensor flags per stage)
+            for i, n in enumerate(range(n0, n1)):
+                self.seg_states[i].copy_(U)
+                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J, self.seg_stages[i], self.seg_tapes[i])
             for i in reversed(range(n1 - n0)):
                 n = n0 + i
-                Tg = temps[i].clone()
-                htr.htr_rk3_step_adjoint(self.ctx, states[i], stages[i], Tg, self.t0 + n * self.dt, self.dt, L, dlnA,
-                                         Jbar, Ubar, pbar, self.adj_work)
+                htr.htr_rk3_step_adjoint(self.ctx, self.seg_states[i], self.seg_stages[i], T, self.t0 + n * self.dt,
+                                         self.dt, L, dlnA, Jbar, Ubar, pbar, self.adj_work, self.seg_tapes[i])
         htr.htr_check(self.ctx)
         return pbar, Ubar
 

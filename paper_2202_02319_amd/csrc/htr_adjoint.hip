@@ -578,7 +578,7 @@ __device__ __forceinline__ void block_sum_to(double v, double* wred, double* dst
 }
 
 template <int NS>
-__global__ __launch_bounds__(BLK) void k_adj_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+__global__ __launch_bounds__(BLK, 2) void k_adj_point(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                                    int nmem, CallArgs A, const double* __restrict__ Ub,
                                                    const double* __restrict__ Tb, const double* __restrict__ pbb,
                                                    const double* __restrict__ ubdb, const double* __restrict__ lamb,

@@ -34,9 +34,12 @@ AdjBufs split(const htr_ctx* c, double* w) {
   return b;
 }
 
+// With a tape view the stage's per-cell fields, temperature and sensor flags
+// are taken from it; otherwise they are recomputed from U (T is the Newton
+// guess cache).
 htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, double tk, const htr_laser* laser,
                    const double* dlnA, const double* lam, double s, double h, double* out, double* pbar,
-                   hipStream_t st) {
+                   hipStream_t st, const TapeView* tv = nullptr) {
   Ctx C{};
   C.ns = c->ns;
   C.M = c->dM;
@@ -50,12 +53,21 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
   a.laser = make_laser(laser, c->n, c->L);
   a.dlnA = dlnA;
   a.flags = c->scheme.flags;
-  HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
-                      c->ws.status, 0, st));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, nullptr,
-                       st));
+  const double* aux = c->ws.aux;
+  const unsigned char* flag = c->ws.flag;
+  const double* Ts = T;
+  if (tv) {
+    aux = tv->aux;
+    flag = tv->flag;
+    Ts = tv->T;
+  } else {
+    HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
+                        c->ws.status, 0, st));
+    HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c,
+                         nullptr, st));
+  }
   const int nth = 4 + c->nr;
-  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, T, c->ws.aux, c->ws.flag, lam, s, h, b.ubd, b.pb,
+  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, Ts, aux, flag, lam, s, h, b.ubd, b.pb,
                         out, b.thpart, nth, C.scheme.psi_c, C.scheme.teno_CT, st));
   HIP_OK(launch_adj_theta(C.mem, 1, b.thpart, nth, pbar, st));
   return HTR_OK;
@@ -87,7 +99,7 @@ htr_status htr_rhs_adjoint(htr_ctx* c, const double* U, double* T_io, double t, 
 
 htr_status htr_rk3_step_adjoint(htr_ctx* c, const double* Un, const double* stages, double* T_io, double t,
                                 double dt, const htr_laser* laser, const double* dlnA_dev, double Jbar,
-                                double* Ubar, double* pbar_acc, double* adj_work, void* stream) {
+                                double* Ubar, double* pbar_acc, double* adj_work, const void* tape, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
   if (!Un || !stages || !T_io || !Ubar || !pbar_acc || !adj_work) return fail(HTR_EINVAL, "NULL pointer");
   if (!std::isfinite(t) || !(dt > 0) || !std::isfinite(Jbar)) return fail(HTR_EINVAL, "need finite t, Jbar and dt > 0");
@@ -103,18 +115,22 @@ htr_status htr_rk3_step_adjoint(htr_ctx* c, const double* Un, const double* stag
   const double bq[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
   // stage 3: U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2, t + dt/2))
   HIP_OK(launch_axpby(n, 2.0 / 3.0, Ubar, 0.0, b.B2, s));
+  TapeView tv[3];
+  for (int k = 0; k < 3 && tape; ++k) tv[k] = tape_view(const_cast<void*>(tape), c->ns, c->N, k);
   st = rhs_adj(c, b, U2, T_io, t + 0.5 * dt, laser, dlnA_dev, Ubar, (2.0 / 3.0) * dt, dt * bq[2] * Jbar, b.B2,
-               pbar_acc, s);
+               pbar_acc, s, tape ? &tv[2] : nullptr);
   if (st) return st;
   HIP_OK(launch_axpby(n, 1.0 / 3.0, Ubar, 0.0, Ubar, s));
   // stage 2: U2 = 3/4 U^n + 1/4 (U1 + dt L(U1, t + dt))
   HIP_OK(launch_axpby(n, 0.25, b.B2, 0.0, b.B1, s));
-  st = rhs_adj(c, b, U1, T_io, t + dt, laser, dlnA_dev, b.B2, 0.25 * dt, dt * bq[1] * Jbar, b.B1, pbar_acc, s);
+  st = rhs_adj(c, b, U1, T_io, t + dt, laser, dlnA_dev, b.B2, 0.25 * dt, dt * bq[1] * Jbar, b.B1, pbar_acc, s,
+               tape ? &tv[1] : nullptr);
   if (st) return st;
   HIP_OK(launch_axpby(n, 0.75, b.B2, 1.0, Ubar, s));
   // stage 1: U1 = U^n + dt L(U^n, t)
   HIP_OK(launch_axpby(n, 1.0, b.B1, 1.0, Ubar, s));
-  return rhs_adj(c, b, Un, T_io, t, laser, dlnA_dev, b.B1, dt, dt * bq[0] * Jbar, Ubar, pbar_acc, s);
+  return rhs_adj(c, b, Un, T_io, t, laser, dlnA_dev, b.B1, dt, dt * bq[0] * Jbar, Ubar, pbar_acc, s,
+                 tape ? &tv[0] : nullptr);
 }
 
 }  // extern "C"

@@ -201,7 +201,7 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
   hipStream_t s = (hipStream_t)stream;
   if (!use_graph) {
     for (int k = 0; k < nsteps; ++k) {
-      htr_status st = rk3(C, b->ws, U, T_io, t_dev, dt_dev, compute_dt, nullptr, nullptr, work, J_dev, s);
+      htr_status st = rk3(C, b->ws, U, T_io, t_dev, dt_dev, compute_dt, nullptr, nullptr, work, J_dev, s, nullptr);
       if (st) return st;
     }
     return HTR_OK;
@@ -215,7 +215,8 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
     HIP_OK(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
     htr_status st = HTR_OK;
     for (int k = 0; k < nsteps && !st; ++k)
-      st = rk3(C, b->ws, U, T_io, t_dev, dt_dev, compute_dt, nullptr, nullptr, work, J_dev, b->gstream);
+      st = rk3(C, b->ws, U, T_io, t_dev, dt_dev, compute_dt, nullptr, nullptr, work, J_dev, b->gstream,
+               nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->gstream, &g);
     if (st) {

@@ -269,7 +269,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
 
 htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t_dev, double* dt_dev,
                int compute_dt, const htr_laser* laser, const double* dlnA, double* work, double* J_dev,
-               hipStream_t s) {
+               hipStream_t s, void* tape) {
   const long long tot = C.total_cells;
   double* U1 = work;
   double* U2 = work + (long long)(C.ns + 4) * tot;
@@ -291,6 +291,13 @@ htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t
     htr_status st = stage(C, w, a, in[k], U, T, out[k], ca[k], cb[k], 0, nullptr, J_dev, bq[k], s,
                           k == 0 && compute_dt, dt_dev);
     if (st) return st;
+    if (tape) {
+      // the stage's per-cell fields, temperature and sensor flags, as its sweeps used them
+      const TapeView tv = tape_view(tape, C.ns, tot, k);
+      HIP_OK(hipMemcpyAsync(tv.aux, w.aux, sizeof(double) * (7 + C.ns) * tot, hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(tv.T, T, sizeof(double) * tot, hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(tv.flag, w.flag, tot, hipMemcpyDeviceToDevice, s));
+    }
   }
   TimedLaunch tl(C.timer, TC_REDUCE, s);
   HIP_OK(launch_advance_time(C.nmem, t_dev, dt_dev, s));
@@ -500,7 +507,26 @@ htr_status htr_rk3_step(htr_ctx* c, double* U, double* T_io, double* t_dev, doub
   Ctx C = view(c);
   htr_laser off{};
   return rk3(C, c->ws, U, T_io, t_dev, dt_dev, compute_dt, laser ? laser : &off, dlnA_dev, work, J_dev,
-             (hipStream_t)stream);
+             (hipStream_t)stream, nullptr);
+}
+
+size_t htr_tape_bytes(const htr_ctx* c) {
+  if (!c) return 0;
+  return tape_bytes(c->ns, c->N);
+}
+
+htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev, double* dt_dev, int compute_dt,
+                              const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
+                              void* tape, void* stream) {
+  if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (!U || !T_io || !t_dev || !dt_dev || !work || !tape) return fail(HTR_EINVAL, "NULL pointer");
+  if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
+  htr_status st = check_laser(laser);
+  if (st) return st;
+  Ctx C = view(c);
+  htr_laser off{};
+  return rk3(C, c->ws, U, T_io, t_dev, dt_dev, compute_dt, laser ? laser : &off, dlnA_dev, work, J_dev,
+             (hipStream_t)stream, tape);
 }
 
 htr_status htr_timing(htr_ctx* c, int enable) {

@@ -83,7 +83,26 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
                  hipStream_t s, int want_dt, double* dt_out);
 htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t_dev, double* dt_dev,
                int compute_dt, const htr_laser* laser, const double* dlnA, double* work, double* J_dev,
-               hipStream_t s);
+               hipStream_t s, void* tape);
+
+// Forward tape of one RK3 step: per stage k the per-cell fields [7 + ns][N],
+// the temperature [N] and the sensor flags [N] that the stage's sweeps used.
+struct TapeView {
+  double* aux;
+  double* T;
+  unsigned char* flag;
+};
+inline size_t tape_bytes(int ns, long long N) {
+  return 3 * (sizeof(double) * (size_t)(8 + ns) * (size_t)N) + 3 * (size_t)N;
+}
+inline TapeView tape_view(void* tape, int ns, long long N, int k) {
+  double* d = static_cast<double*>(tape);
+  TapeView v;
+  v.aux = d + (long long)k * (8 + ns) * N;
+  v.T = v.aux + (long long)(7 + ns) * N;
+  v.flag = reinterpret_cast<unsigned char*>(d + 3LL * (8 + ns) * N) + (long long)k * N;
+  return v;
+}
 
 }  // namespace htr
 

@@ -188,11 +188,27 @@ def htr_rhs_adjoint(ctx, U, T_io, t, laser, dlnA_dev, lam, s, h, Ubar_acc, pbar_
 
 
 def htr_rk3_step_adjoint(ctx, Un, stages, T_io, t, dt, laser, dlnA_dev, Jbar, Ubar, pbar_acc, adj_work,
-                         stream=None):
+                         tape=None, stream=None):
     L = make_laser(laser)
     check(ctx.lib.htr_rk3_step_adjoint(ctx.h, _ptr(Un), _ptr(stages), _ptr(T_io), float(t), float(dt),
                                        C.byref(L) if L else None, _ptr(dlnA_dev), float(Jbar), _ptr(Ubar),
-                                       _ptr(pbar_acc), _ptr(adj_work), _stream(stream)))
+                                       _ptr(pbar_acc), _ptr(adj_work), _ptr(tape), _stream(stream)))
+
+
+def htr_tape_bytes(ctx):
+    return int(ctx.lib.htr_tape_bytes(ctx.h))
+
+
+def new_tape(ctx, device="cuda"):
+    """Device buffer for the forward tape of one RK3 step."""
+    return torch.empty((htr_tape_bytes(ctx) + 7) // 8, dtype=torch.float64, device=device)
+
+
+def htr_rk3_step_taped(ctx, U, T_io, t_dev, dt_dev, compute_dt, laser, dlnA_dev, work, J_dev, tape, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rk3_step_taped(ctx.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dt_dev), int(compute_dt),
+                                     C.byref(L) if L else None, _ptr(dlnA_dev), _ptr(work), _ptr(J_dev), _ptr(tape),
+                                     _stream(stream)))
 
 
 def _i3(v):

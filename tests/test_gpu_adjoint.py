@@ -76,10 +76,12 @@ def test_rhs_adjoint_dot_product(name, kw, flags):
     assert abs(rhs_par - lhs_p) <= 1e-10 * max(scale_p, 1e-300), (rhs_par, lhs_p)
 
 
-@pytest.mark.parametrize("name,kw,flags", CASES[:3])
-def test_rk3_step_adjoint_dot_product(name, kw, flags):
+@pytest.mark.parametrize("taped", [False, True])
+@pytest.mark.parametrize("name,kw,flags", CASES[:3] + CASES[6:7])
+def test_rk3_step_adjoint_dot_product(name, kw, flags, taped):
     """One RK3 step with a fixed dt: <Ubar, dU'> + Jbar dJ (oracle tangent)
-    equals <Ubar_0, dU> + <thetabar, dtheta> (GPU adjoint)."""
+    equals <Ubar_0, dU> + <thetabar, dtheta> (GPU adjoint), with the stages'
+    per-cell fields recomputed or taken from the forward tape."""
     case = _case(kw, flags)
     o = Oracle(case)
     U0 = o.prim_to_cons()
@@ -96,11 +98,15 @@ def test_rk3_step_adjoint_dot_product(name, kw, flags):
     g = htr.Context.from_case(case)
     Ud, Td = dev(U0), dev(case.T)
     work = g.new_work()
-    htr.htr_rk3_step(g, Ud.clone(), Td.clone(), dev([t]), dev([dt]), 0, case.laser, None, work, None)
+    tape = htr.new_tape(g) if taped else None
+    if taped:
+        htr.htr_rk3_step_taped(g, Ud.clone(), Td.clone(), dev([t]), dev([dt]), 0, case.laser, None, work, None, tape)
+    else:
+        htr.htr_rk3_step(g, Ud.clone(), Td.clone(), dev([t]), dev([dt]), 0, case.laser, None, work, None)
     Ubar = dev(Ubar_in)
     pbar = torch.zeros(4 + case.mech.nr, dtype=torch.float64, device="cuda")
     htr.htr_rk3_step_adjoint(g, Ud, work, Td.clone(), t, dt, case.laser, None, Jbar, Ubar, pbar,
-                             htr.new_adjoint_work(g))
+                             htr.new_adjoint_work(g), tape)
     htr.htr_check(g)
     rhs = float((host(Ubar) * dU).sum() + (host(pbar) * dth).sum())
     scale = float(np.abs(Ubar_in * dU1).sum() + abs(Jbar * dJ))
