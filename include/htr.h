@@ -225,8 +225,9 @@ htr_status htr_rhs_adjoint(htr_ctx* ctx, const double* U, double* T_io, double t
                            double* pbar_acc, double* adj_work, void* stream);
 
 /* Bytes of a forward tape of one step: per stage the per-cell fields
- * [7 + ns][N], the temperature [N] (doubles) and the sensor flags [N]
- * (bytes, after all the doubles). */
+ * [7 + ns][N] and the temperature [N] (doubles), then per stage the sensor
+ * flags [N], then per stage the TENO cut-off patterns [3][nv][N] (bytes: per
+ * axis, variable and face, indexed by the face's upper cell). */
 size_t htr_tape_bytes(const htr_ctx* ctx);
 /* htr_rk3_step that also records its tape (device, >= htr_tape_bytes). */
 htr_status htr_rk3_step_taped(htr_ctx* ctx, double* U, double* T_io, double* t_dev, double* dt_dev, int compute_dt,
@@ -238,9 +239,9 @@ htr_status htr_rk3_step_taped(htr_ctx* ctx, double* U, double* T_io, double* t_d
  * buffer as that htr_rk3_step left it (U1 then U2).  Ubar [nv][N] holds the
  * cotangent of U^{n+1} on entry and that of U^n on return; pbar_acc[4+nr]
  * accumulates the parameter cotangent.  tape (nullable) is the step's tape
- * from htr_rk3_step_taped: the stages' per-cell fields, temperatures and
- * sensor flags are then taken from it instead of being recomputed (T_io is
- * then not used). */
+ * from htr_rk3_step_taped: the stages' per-cell fields, temperatures, sensor
+ * flags and TENO cut-off patterns are then taken from it instead of being
+ * recomputed (T_io is then not used). */
 htr_status htr_rk3_step_adjoint(htr_ctx* ctx, const double* Un, const double* stages, double* T_io, double t,
                                 double dt, const htr_laser* laser, const double* dlnA_dev, double Jbar,
                                 double* Ubar, double* pbar_acc, double* adj_work, const void* tape, void* stream);

@@ -265,7 +265,8 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
                                                    double psi_c, double CT, double* s_ud, double* s_p, double* s_c,
                                                    double* s_U, double* s_L, double* s_al, unsigned char* s_fl,
                                                    unsigned char* s_te, unsigned char* s_db, double* s_ub,
-                                                   double& pbu, double& pbp, double& pbc) {
+                                                   double& pbu, double& pbp, double& pbc,
+                                                   const unsigned char* __restrict__ tbits) {
   constexpr int NV = NS + 4;
   const int t = threadIdx.x;
   const int T[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
@@ -299,13 +300,21 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
   // this thread's faces: slot fb_d = j + 2 (0 .. T_d + 4) for the face between tile positions
   // j-1 and j, whose stencil covers box positions fb_d .. fb_d + 5 along d
   int fe0[FPTA];
+  long long fq[FPTA];   // the face's upper cell (index of the forward's taped cut-off patterns)
 #pragma unroll
   for (int k = 0; k < FPTA; ++k) {
     const int f = t + k * BLK;
     fe0[k] = -1;
+    fq[k] = 0;
     if (f < F) {
       const int fb[3] = {f % FB[0], (f / FB[0]) % FB[1], f / (FB[0] * FB[1])};
       fe0[k] = fb[0] + B[0] * (fb[1] + B[1] * fb[2]);
+      if (tbits) {
+        int g[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a] = wrapi(o[a] + fb[a] - (a == d ? 2 : 0), G.n[a]);
+        fq[k] = ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
+      }
       const int e0 = fe0[k];
       bool te;
       if (flags & HTR_FORCE_TENO) te = true;
@@ -379,6 +388,10 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
       if (fe0[k] < 0) continue;
       const int f = t + k * BLK;
       if (!(s_te[f] & 1)) continue;
+      if (tbits) {
+        s_db[f] = tbits[(long long)(d * NV + v) * N + fq[k]];
+        continue;
+      }
       const int e0 = fe0[k];
       const double al = s_al[f];
       double fp[6], fm[6];
@@ -463,7 +476,8 @@ __global__ __launch_bounds__(BLK, 2) void k_adj_conv_tiled(const Member* __restr
                                                            const unsigned char* __restrict__ flagb,
                                                            const double* __restrict__ lamb, double s,
                                                            double* __restrict__ ubdb, double* __restrict__ pbb,
-                                                           double psi_c, double CT) {
+                                                           const unsigned char* __restrict__ tbitsb, double psi_c,
+                                                           double CT) {
   constexpr int NV = NS + 4, NAUX = 7 + NS, NPB = 8 + NS;
   __shared__ double s_ud[EXTA], s_p[EXTA], s_c[EXTA], s_U[EXTA], s_L[EXTA], s_al[FACEA];
   __shared__ unsigned char s_fl[EXTA], s_te[FACEA], s_db[FACEA];
@@ -482,18 +496,19 @@ __global__ __launch_bounds__(BLK, 2) void k_adj_conv_tiled(const Member* __restr
   const double* aux = auxb + NAUX * G.off;
   const unsigned char* flag = flagb + G.off;
   const double* lam = lamb + NV * G.off;
+  const unsigned char* tbits = tbitsb ? tbitsb + 3LL * NV * G.off : nullptr;
   for (int v = 0; v < NV; ++v) s_ub[v * BLK + t] = 0.0;
   double pbu[3] = {0.0, 0.0, 0.0}, pbp = 0.0, pbc = 0.0;
   const unsigned flags = A.flags;
   if (G.act[0])
     adj_conv_tiled_dir<NS, 0>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[0], pbp, pbc);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[0], pbp, pbc, tbits);
   if (G.act[1])
     adj_conv_tiled_dir<NS, 1>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[1], pbp, pbc);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[1], pbp, pbc, tbits);
   if (G.act[2])
     adj_conv_tiled_dir<NS, 2>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[2], pbp, pbc);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[2], pbp, pbc, tbits);
   if (!valid) return;
   const long long q = ((long long)gc[2] * G.n[1] + gc[1]) * G.n[0] + gc[0];
   double* ubd = ubdb + NV * G.off;
@@ -971,10 +986,10 @@ template <int NS>
 static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
                         const CallArgs& a,
                         const double* U, const double* T, const double* aux, const unsigned char* flag,
-                        const double* lam, double s, double h, double* ubd, double* pbv, double* out,
-                        double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
+                        const unsigned char* bits, const double* lam, double s, double h, double* ubd, double* pbv,
+                        double* out, double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
   hipLaunchKernelGGL((k_adj_conv_tiled<NS>), dim3(ntblocks), dim3(BLK), 0, st, mem, nmem, a, U, aux, flag, lam, s,
-                     ubd, pbv, psi_c, CT);
+                     ubd, pbv, bits, psi_c, CT);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!(a.flags & HTR_VISC_OFF)) {
@@ -990,10 +1005,11 @@ static hipError_t adj_t(const MechTables* M, const Member* mem, int nmem, int nb
 hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
                           const CallArgs& a,
                           const double* U, const double* T, const double* aux, const unsigned char* flag,
-                          const double* lam, double s, double h, double* ubd, double* pbv, double* out,
-                          double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
-#define C_(NS) \
-  adj_t<NS>(M, mem, nmem, nblocks, ntblocks, a, U, T, aux, flag, lam, s, h, ubd, pbv, out, thpart, nth, psi_c, CT, st)
+                          const unsigned char* bits, const double* lam, double s, double h, double* ubd, double* pbv,
+                          double* out, double* thpart, int nth, double psi_c, double CT, hipStream_t st) {
+#define C_(NS)                                                                                                   \
+  adj_t<NS>(M, mem, nmem, nblocks, ntblocks, a, U, T, aux, flag, bits, lam, s, h, ubd, pbv, out, thpart, nth, psi_c, \
+            CT, st)
   switch (ns) {
     case 1: return C_(1); case 2: return C_(2); case 3: return C_(3);
     case 4: return C_(4); case 5: return C_(5); case 6: return C_(6);

@@ -55,10 +55,12 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
   a.flags = c->scheme.flags;
   const double* aux = c->ws.aux;
   const unsigned char* flag = c->ws.flag;
+  const unsigned char* bits = nullptr;
   const double* Ts = T;
   if (tv) {
     aux = tv->aux;
     flag = tv->flag;
+    bits = tv->bits;
     Ts = tv->T;
   } else {
     HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T, c->ws.aux, c->ws.src, nullptr, nullptr, nullptr,
@@ -67,7 +69,7 @@ htr_status rhs_adj(htr_ctx* c, const AdjBufs& b, const double* U, double* T, dou
                          nullptr, st));
   }
   const int nth = 4 + c->nr;
-  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, Ts, aux, flag, lam, s, h, b.ubd, b.pb,
+  HIP_OK(launch_adjoint(C.ns, C.M, C.mem, 1, C.nblocks, c->ntblocks, a, U, Ts, aux, flag, bits, lam, s, h, b.ubd, b.pb,
                         out, b.thpart, nth, C.scheme.psi_c, C.scheme.teno_CT, st));
   HIP_OK(launch_adj_theta(C.mem, 1, b.thpart, nth, pbar, st));
   return HTR_OK;

@@ -236,7 +236,7 @@ TimedLaunch::~TimedLaunch() {
 // want_dt: the per-cell kernel also reduces the stable step and writes dt_dev.
 htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const double* U, const double* Un,
                  double* T, double* out, double ca, double cb, int rhs_only, double* hrr, double* J_dev,
-                 double jcoef, hipStream_t s, int want_dt, double* dt_out) {
+                 double jcoef, hipStream_t s, int want_dt, double* dt_out, unsigned char* teno_bits) {
   const bool need_red = J_dev != nullptr || want_dt;
   {
     TimedLaunch tl(C.timer, TC_POINT, s);
@@ -254,7 +254,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   }
   {
     TimedLaunch tl(C.timer, TC_CONV, s);
-    HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, w.aux, w.src, w.flag, w.part,
+    HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, w.aux, w.src, w.flag, w.part, teno_bits,
                        C.scheme.psi_c,
                        C.scheme.teno_CT, s));
   }
@@ -288,12 +288,13 @@ htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t
   double* out[3] = {U1, U2, U};
   for (int k = 0; k < 3; ++k) {
     a.tcoef = tc[k];
+    TapeView tv{};
+    if (tape) tv = tape_view(tape, C.ns, tot, k);
     htr_status st = stage(C, w, a, in[k], U, T, out[k], ca[k], cb[k], 0, nullptr, J_dev, bq[k], s,
-                          k == 0 && compute_dt, dt_dev);
+                          k == 0 && compute_dt, dt_dev, tape ? tv.bits : nullptr);
     if (st) return st;
     if (tape) {
       // the stage's per-cell fields, temperature and sensor flags, as its sweeps used them
-      const TapeView tv = tape_view(tape, C.ns, tot, k);
       HIP_OK(hipMemcpyAsync(tv.aux, w.aux, sizeof(double) * (7 + C.ns) * tot, hipMemcpyDeviceToDevice, s));
       HIP_OK(hipMemcpyAsync(tv.T, T, sizeof(double) * tot, hipMemcpyDeviceToDevice, s));
       HIP_OK(hipMemcpyAsync(tv.flag, w.flag, tot, hipMemcpyDeviceToDevice, s));

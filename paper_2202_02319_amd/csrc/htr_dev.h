@@ -167,10 +167,12 @@ hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem
 hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, const double* aux, int ns,
                          unsigned char* flag,
                          double* grad, double theta_c, double* theta_out, hipStream_t s);
+// bits (nullable): TENO cut-off patterns [3][nv][N] bytes, per axis, variable
+// and face (indexed by the face's upper cell); written for TENO faces only.
 hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a,
                        const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
-                       double psi_c, double CT, hipStream_t s);
+                       unsigned char* bits, double psi_c, double CT, hipStream_t s);
 hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a,
                        const double* U, const double* Un, const double* T, const double* aux, const double* grad,
@@ -185,9 +187,11 @@ void default_tile_shape(const int act[3], int shape[3]);
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);
+// bits (nullable): the forward's TENO cut-off patterns (as launch_conv wrote them).
 hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
                           const CallArgs& a,
                           const double* U, const double* T, const double* aux, const unsigned char* flag,
+                          const unsigned char* bits,
                           const double* lam, double s, double h, double* ubd, double* pbv, double* out,
                           double* thpart, int nth, double psi_c, double CT, hipStream_t st);
 hipError_t launch_adj_theta(const Member* mem, int nmem, const double* thpart, int nth, double* pbar,

@@ -80,27 +80,31 @@ htr_status ws_alloc(Workspace& w, int ns, long long N, int nblocks, int nmem);
 void ws_free(Workspace& w);
 htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const double* U, const double* Un, double* T,
                  double* out, double ca, double cb, int rhs_only, double* hrr, double* J_dev, double jcoef,
-                 hipStream_t s, int want_dt, double* dt_out);
+                 hipStream_t s, int want_dt, double* dt_out, unsigned char* teno_bits = nullptr);
 htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t_dev, double* dt_dev,
                int compute_dt, const htr_laser* laser, const double* dlnA, double* work, double* J_dev,
                hipStream_t s, void* tape);
 
 // Forward tape of one RK3 step: per stage k the per-cell fields [7 + ns][N],
-// the temperature [N] and the sensor flags [N] that the stage's sweeps used.
+// the temperature [N], the sensor flags [N] and the TENO cut-off patterns
+// [3][nv][N] that the stage's sweeps used (doubles first, then the bytes).
 struct TapeView {
   double* aux;
   double* T;
   unsigned char* flag;
+  unsigned char* bits;
 };
 inline size_t tape_bytes(int ns, long long N) {
-  return 3 * (sizeof(double) * (size_t)(8 + ns) * (size_t)N) + 3 * (size_t)N;
+  return 3 * (sizeof(double) * (size_t)(8 + ns) * (size_t)N) + 3 * (size_t)N + 9 * (size_t)(ns + 4) * (size_t)N;
 }
 inline TapeView tape_view(void* tape, int ns, long long N, int k) {
   double* d = static_cast<double*>(tape);
   TapeView v;
   v.aux = d + (long long)k * (8 + ns) * N;
   v.T = v.aux + (long long)(7 + ns) * N;
-  v.flag = reinterpret_cast<unsigned char*>(d + 3LL * (8 + ns) * N) + (long long)k * N;
+  unsigned char* bytes = reinterpret_cast<unsigned char*>(d + 3LL * (8 + ns) * N);
+  v.flag = bytes + (long long)k * N;
+  v.bits = bytes + 3LL * N + (long long)k * 3 * (ns + 4) * N;
   return v;
 }
 

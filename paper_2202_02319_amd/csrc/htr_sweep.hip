@@ -84,9 +84,15 @@ void set_tiles(Member& M, const int* shape, int* tblocks) {
 
 // TENO6 face flux on the local Lax-Friedrichs split, kept out of line so the
 // (far more common) central faces do not carry its register footprint.
-__device__ __attribute__((noinline)) double teno_face(double f0, double f1, double f2, double f3, double f4,
-                                                     double f5, double u0, double u1, double u2, double u3,
-                                                     double u4, double u5, double al, double CT) {
+// Also returns the cut-off pattern (bits 0-3: the + side's kept candidates,
+// bits 4-7: the - side's), which a forward tape keeps for the adjoint.
+struct TenoFace {
+  double F;
+  unsigned bits;
+};
+__device__ __attribute__((noinline)) TenoFace teno_face(double f0, double f1, double f2, double f3, double f4,
+                                                        double f5, double u0, double u1, double u2, double u3,
+                                                        double u4, double u5, double al, double CT) {
   const double f6[6] = {f0, f1, f2, f3, f4, f5}, u6[6] = {u0, u1, u2, u3, u4, u5};
   double fp[6], fm[6];
 #pragma unroll
@@ -94,7 +100,16 @@ __device__ __attribute__((noinline)) double teno_face(double f0, double f1, doub
     fp[mm] = 0.5 * (f6[mm] + al * u6[mm]);
     fm[5 - mm] = 0.5 * (f6[mm] - al * u6[mm]);
   }
-  return teno6(fp, CT) + teno6(fm, CT);
+  double wp[4], qp[4], wm[4], qm[4];
+  teno6_core(fp, CT, wp, qp);
+  teno6_core(fm, CT, wm, qm);
+  TenoFace r;
+  r.F = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
+        (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
+  r.bits = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.bits |= (wp[k] > 0.0 ? 1u : 0u) << k | (wm[k] > 0.0 ? 1u : 0u) << (k + 4);
+  return r;
 }
 
 
@@ -117,11 +132,12 @@ constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
 // written once (the loading thread keeps that cell's velocity and pressure
 // in registers), and every face flux is evaluated once from them, all
 // directions together.
-template <int NS>
+template <int NS, bool TAPE>
 __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem, int nmem, const CallArgs& A,
                                           const double* __restrict__ Ub, const double* __restrict__ auxb,
                                           const double* __restrict__ srcb, const unsigned char* __restrict__ flagb,
-                                          double* __restrict__ partb, double psi_c, double CT) {
+                                          double* __restrict__ partb, unsigned char* __restrict__ bitsb, double psi_c,
+                                          double CT) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
@@ -171,6 +187,9 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   const double* aux = auxb + NAUX * G.off;
   const unsigned char* flag = flagb + G.off;
   const double* src = srcb + (NS + 1) * G.off;
+  // TENO cut-off patterns per axis, variable and face (indexed by the face's
+  // upper cell), when a forward tape asks for them
+  unsigned char* bits = TAPE ? bitsb + 3LL * NV * G.off : nullptr;
   long long qc;
   {
     int g[3];
@@ -238,7 +257,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   __syncthreads();
   // this thread's faces: stencil start slot, stride along the axis, hybrid
   // decision and Lax-Friedrichs speed
-  int fe0[XFPT], fst[XFPT];
+  int fe0[XFPT], fst[XFPT], fdx[XFPT];
+  long long fq[XFPT];
   unsigned fte = 0;
   double fal[XFPT];
   const unsigned flags = A.flags;
@@ -247,6 +267,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     const int f = t + k * BLK;
     fe0[k] = -1;
     fst[k] = 1;
+    fdx[k] = 0;
+    fq[k] = 0;
     fal[k] = 0.0;
     if (f < Ftot) {
       const int d = f < foff[1] ? 0 : (f < foff[2] ? 1 : 2);
@@ -259,6 +281,13 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
       const int bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
       fe0[k] = e0;
       fst[k] = bs;
+      fdx[k] = d;
+      if (TAPE) {
+        int g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
+        fq[k] = lin(G, g);
+      }
       bool te;
       if (flags & HTR_FORCE_TENO) te = true;
       else if (flags & HTR_FORCE_CENTRAL) te = false;
@@ -338,8 +367,10 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         double u6[6];
 #pragma unroll
         for (int mm = 0; mm < 6; ++mm) u6[mm] = s_U[e0 + mm * bs];
-        Fh = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4], u6[5],
-                       fal[k], CT);
+        const TenoFace r = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4],
+                                     u6[5], fal[k], CT);
+        Fh = r.F;
+        if (TAPE) bits[(long long)(fdx[k] * NV + v) * N + fq[k]] = (unsigned char)r.bits;
       }
       sF[t + k * BLK] = Fh;
     }
@@ -354,20 +385,20 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   }
 }
 
-// Grid-stride over the nlog tiles: one pass when the grid has one block per
-// tile, persistent blocks when it has fewer.
-template <int NS, bool PERSIST>
+// MODE 0: one block per tile; 1: persistent blocks striding over the nlog
+// tiles; 2: one block per tile, also writing the TENO cut-off patterns.
+template <int NS, int MODE>
 __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                               int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
                                               const double* __restrict__ auxb, const double* __restrict__ srcb,
                                               const unsigned char* __restrict__ flagb, double* __restrict__ partb,
-                                              double psi_c, double CT) {
-  if (!PERSIST) {
-    conv_tile<NS>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, psi_c, CT);
+                                              unsigned char* __restrict__ bitsb, double psi_c, double CT) {
+  if (MODE != 1) {
+    conv_tile<NS, MODE == 2>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT);
     return;
   }
   for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
-    conv_tile<NS>(bl, mem, nmem, A, Ub, auxb, srcb, flagb, partb, psi_c, CT);
+    conv_tile<NS, false>(bl, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT);
     __syncthreads();   // the next tile reuses the LDS
   }
 }
@@ -597,13 +628,16 @@ static int grid_of(int nblocks, int grid) { return (grid <= 0 || grid > nblocks)
 template <int NS>
 static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid, const CallArgs& a,
                          const double* U, const double* aux, const double* src, const unsigned char* flag,
-                         double* part, double psi_c, double CT, hipStream_t s) {
-  if (grid < ntblocks)
-    hipLaunchKernelGGL((k_conv<NS, true>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, psi_c, CT);
+                         double* part, unsigned char* bits, double psi_c, double CT, hipStream_t s) {
+  if (bits)   // taped: one block per tile
+    hipLaunchKernelGGL((k_conv<NS, 2>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT);
+  else if (grid < ntblocks)
+    hipLaunchKernelGGL((k_conv<NS, 1>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT);
   else
-    hipLaunchKernelGGL((k_conv<NS, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, psi_c, CT);
+    hipLaunchKernelGGL((k_conv<NS, 0>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT);
   return hipGetLastError();
 }
 
@@ -622,9 +656,10 @@ static hipError_t diff_t(const MechTables* M, const Member* mem, int nmem, int n
 
 hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a, const double* U, const double* aux, const double* src,
-                       const unsigned char* flag, double* part, double psi_c, double CT, hipStream_t s) {
+                       const unsigned char* flag, double* part, unsigned char* bits, double psi_c, double CT,
+                       hipStream_t s) {
   grid = grid_of(ntblocks, grid);
-#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, grid, a, U, aux, src, flag, part, psi_c, CT, s)
+#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, grid, a, U, aux, src, flag, part, bits, psi_c, CT, s)
   HTR_NS_SWITCH(ns, C_);
 #undef C_
 }
