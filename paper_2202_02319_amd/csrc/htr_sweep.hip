@@ -82,37 +82,6 @@ void set_tiles(Member& M, const int* shape, int* tblocks) {
   *tblocks += nb;
 }
 
-// TENO6 face flux on the local Lax-Friedrichs split, kept out of line so the
-// (far more common) central faces do not carry its register footprint.
-// Also returns the cut-off pattern (bits 0-3: the + side's kept candidates,
-// bits 4-7: the - side's), which a forward tape keeps for the adjoint.
-struct TenoFace {
-  double F;
-  unsigned bits;
-};
-__device__ __attribute__((noinline)) TenoFace teno_face(double f0, double f1, double f2, double f3, double f4,
-                                                        double f5, double u0, double u1, double u2, double u3,
-                                                        double u4, double u5, double al, double CT) {
-  const double f6[6] = {f0, f1, f2, f3, f4, f5}, u6[6] = {u0, u1, u2, u3, u4, u5};
-  double fp[6], fm[6];
-#pragma unroll
-  for (int mm = 0; mm < 6; ++mm) {
-    fp[mm] = 0.5 * (f6[mm] + al * u6[mm]);
-    fm[5 - mm] = 0.5 * (f6[mm] - al * u6[mm]);
-  }
-  double wp[4], qp[4], wm[4], qm[4];
-  teno6_core(fp, CT, wp, qp);
-  teno6_core(fm, CT, wm, qm);
-  TenoFace r;
-  r.F = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
-        (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
-  r.bits = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) r.bits |= (wp[k] > 0.0 ? 1u : 0u) << k | (wm[k] > 0.0 ? 1u : 0u) << (k + 4);
-  return r;
-}
-
-
 __device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
   return ((long long)g[2] * G.n[1] + g[1]) * G.n[0] + g[0];
 }
@@ -141,6 +110,9 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
+  __shared__ double s_al[XFACE_MAX];   // LF speed of the TENO faces
+  __shared__ short s_tl[XFACE_MAX];    // the tile's TENO faces
+  __shared__ int s_nt;
   // before the variable loop the same memory holds the LF node speed, the
   // pressure and the sensor flags
   double* s_spd = s_U;
@@ -254,40 +226,38 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
       s_fl[as[k]] = flag[aq[k]];
     }
   }
+  if (t == 0) s_nt = 0;
   __syncthreads();
-  // this thread's faces: stencil start slot, stride along the axis, hybrid
-  // decision and Lax-Friedrichs speed
-  int fe0[XFPT], fst[XFPT], fdx[XFPT];
-  long long fq[XFPT];
+  // face f of the list: axis, stencil start slot (stencil positions j-3..j+2
+  // of the tile = box positions j..j+5 along d), stride along the axis, and
+  // tile position of the face's upper cell
+  auto face = [&](int f, int& d, int& e0, int& bs, int fb[3]) {
+    d = f < foff[1] ? 0 : (f < foff[2] ? 1 : 2);
+    const int r = f - foff[d];
+    const int F0 = T[0] + (d == 0 ? 1 : 0), F1 = T[1] + (d == 1 ? 1 : 0);
+    fb[0] = r % F0;
+    fb[1] = (r / F0) % F1;
+    fb[2] = r / (F0 * F1);
+    e0 = bslot(d, fb[0], fb[1], fb[2]);
+    const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
+    bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
+  };
+  // this thread's faces: stencil start slot, stride, hybrid decision; TENO
+  // faces are also listed (with their Lax-Friedrichs speed) so that each
+  // variable's TENO work is spread evenly over the block
+  int fe0[XFPT], fst[XFPT];
   unsigned fte = 0;
-  double fal[XFPT];
   const unsigned flags = A.flags;
 #pragma unroll
   for (int k = 0; k < XFPT; ++k) {
     const int f = t + k * BLK;
     fe0[k] = -1;
     fst[k] = 1;
-    fdx[k] = 0;
-    fq[k] = 0;
-    fal[k] = 0.0;
     if (f < Ftot) {
-      const int d = f < foff[1] ? 0 : (f < foff[2] ? 1 : 2);
-      const int r = f - foff[d];
-      const int F0 = T[0] + (d == 0 ? 1 : 0), F1 = T[1] + (d == 1 ? 1 : 0);
-      const int fb[3] = {r % F0, (r / F0) % F1, r / (F0 * F1)};
-      // stencil positions j-3..j+2 of the tile = box positions j..j+5 along d
-      const int e0 = bslot(d, fb[0], fb[1], fb[2]);
-      const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
-      const int bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
+      int d, e0, bs, fb[3];
+      face(f, d, e0, bs, fb);
       fe0[k] = e0;
       fst[k] = bs;
-      fdx[k] = d;
-      if (TAPE) {
-        int g[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
-        fq[k] = lin(G, g);
-      }
       bool te;
       if (flags & HTR_FORCE_TENO) te = true;
       else if (flags & HTR_FORCE_CENTRAL) te = false;
@@ -304,7 +274,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         double al = s_spd[e0];
 #pragma unroll
         for (int mm = 1; mm < 6; ++mm) al = fmax(al, s_spd[e0 + mm * bs]);
-        fal[k] = al;
+        s_al[f] = al;
+        s_tl[atomicAdd(&s_nt, 1)] = (short)f;
       }
     }
   }
@@ -329,6 +300,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   double nsrc = valid ? src[q] : 0.0;
   double* part = partb + NV * G.off;
   __syncthreads();   // the decisions have read the node speeds, pressures and flags
+  const int nteno = s_nt;
 #pragma unroll 1
   for (int v = 0; v < NV; ++v) {
 #pragma unroll
@@ -351,28 +323,47 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     }
     __syncthreads();
     double* sF = s_F[v & 1];
+    // central faces: this thread's own
 #pragma unroll
     for (int k = 0; k < XFPT; ++k) {
-      if (fe0[k] < 0) continue;
+      if (fe0[k] < 0 || ((fte >> k) & 1u)) continue;
       const int e0 = fe0[k], bs = fst[k];
       double f6[6];
 #pragma unroll
       for (int mm = 0; mm < 6; ++mm) f6[mm] = s_Fn[e0 + mm * bs];
-      double Fh;
-      if (!((fte >> k) & 1u)) {
-        // the face value goes through LDS before it is differenced, so its
-        // last rounding cannot be fused into the difference
-        Fh = (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
-      } else {
-        double u6[6];
+      // the face value goes through LDS before it is differenced, so its
+      // last rounding cannot be fused into the difference
+      sF[t + k * BLK] =
+          (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
+    }
+    // TENO faces: the tile's list, dealt round-robin over the block
+    for (int i = t; i < nteno; i += BLK) {
+      const int f = s_tl[i];
+      int d, e0, bs, fb[3];
+      face(f, d, e0, bs, fb);
+      const double al = s_al[f];
+      double fp[6], fm[6];
 #pragma unroll
-        for (int mm = 0; mm < 6; ++mm) u6[mm] = s_U[e0 + mm * bs];
-        const TenoFace r = teno_face(f6[0], f6[1], f6[2], f6[3], f6[4], f6[5], u6[0], u6[1], u6[2], u6[3], u6[4],
-                                     u6[5], fal[k], CT);
-        Fh = r.F;
-        if (TAPE) bits[(long long)(fdx[k] * NV + v) * N + fq[k]] = (unsigned char)r.bits;
+      for (int mm = 0; mm < 6; ++mm) {
+        const double f6 = s_Fn[e0 + mm * bs], u6 = s_U[e0 + mm * bs];
+        fp[mm] = 0.5 * (f6 + al * u6);
+        fm[5 - mm] = 0.5 * (f6 - al * u6);
       }
-      sF[t + k * BLK] = Fh;
+      double wp[4], qp[4], wm[4], qm[4];
+      teno6_core(fp, CT, wp, qp);
+      teno6_core(fm, CT, wm, qm);
+      sF[f] = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
+              (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
+      if (TAPE) {
+        // the cut-off pattern: bits 0-3 the + side's kept candidates, 4-7 the - side's
+        unsigned pat = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pat |= (wp[k] > 0.0 ? 1u : 0u) << k | (wm[k] > 0.0 ? 1u : 0u) << (k + 4);
+        int g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
+        bits[(long long)(d * NV + v) * N + lin(G, g)] = (unsigned char)pat;
+      }
     }
     __syncthreads();
     if (valid) {
