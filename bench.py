@@ -268,7 +268,7 @@ def main():
                     help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (ensemble members or grid blocks "
+        print("bench.py measures one GPU: the library has no multi-GPU path (ensemble members or grid blocks "
               "would shard across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
