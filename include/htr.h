@@ -69,6 +69,8 @@ typedef enum {
 #define HTR_VISC_OFF      2u   /* no diffusive fluxes                                      */
 #define HTR_FORCE_CENTRAL 4u   /* central flux on every face                               */
 #define HTR_FORCE_TENO    8u   /* TENO6 on every face                                      */
+#define HTR_WENO3Z       16u   /* WENO3-Z instead of TENO6 where the scheme captures shocks
+                                  (Sec. 5.2's alternative; no adjoint: HTR_EUNSUPPORTED)    */
 
 typedef struct htr_ctx htr_ctx;
 typedef struct htr_batch htr_batch;

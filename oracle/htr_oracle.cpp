@@ -51,7 +51,7 @@ static const double P0 = 101325.0;   // reference pressure of the standard state
 static const double PI = 3.14159265358979323846;
 
 enum { OK = 0, EINVAL = 1, ENONFINITE = 4, ENEWTON = 5, ETRANGE = 6 };
-enum { CHEM_OFF = 1u, VISC_OFF = 2u, FORCE_CENTRAL = 4u, FORCE_TENO = 8u };
+enum { CHEM_OFF = 1u, VISC_OFF = 2u, FORCE_CENTRAL = 4u, FORCE_TENO = 8u, WENO3Z = 16u };
 
 // ------------------------------------------------------------- dual numbers
 struct Dual {
@@ -324,6 +324,24 @@ static S laser_q(const Case& C, const Params<S>& P, int i, int j, int k, double 
          std::exp(-0.5 * tt * tt);
 }
 
+// ----------------------------------------------------------------- WENO3-Z
+// Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges 2013), the
+// paper's alternative shock-capturing scheme (Sec. 5.2), from f_{i-1}, f_i,
+// f_{i+1} = f[1..3] of the six-point face stencil: candidates on {i-1, i} and
+// {i, i+1} with optimal weights 1/3 and 2/3, smoothness indicators the
+// squared first differences, global indicator tau = |beta_0 - beta_1|,
+// alpha_k = d_k (1 + tau / (beta_k + eps)).
+template <class S> static S weno3z(const S* f) {
+  S q0 = (-f[1] + 3.0 * f[2]) / 2.0;
+  S q1 = (f[2] + f[3]) / 2.0;
+  S b0 = (f[2] - f[1]) * (f[2] - f[1]);
+  S b1 = (f[3] - f[2]) * (f[3] - f[2]);
+  S tau = fabs(b0 - b1);
+  S a0 = (1.0 / 3.0) * (1.0 + tau / (b0 + 1e-40));
+  S a1 = (2.0 / 3.0) * (1.0 + tau / (b1 + 1e-40));
+  return (a0 * q0 + a1 * q1) / (a0 + a1);
+}
+
 // ------------------------------------------------------------------- TENO6
 // Reconstruction at x_{i+1/2} from f[0..5] = f_{i-2..i+3} (Fu et al. 2016):
 // four candidate stencils, Jiang-Shu smoothness of each, sixth-order global
@@ -485,7 +503,7 @@ static int conv_flux(const Case& C, const S* U, const Fields<S>& F, int d, const
       fp[m] = 0.5 * (fl + alpha * Uk[m * nv + v]);
       fm[5 - m] = 0.5 * (fl - alpha * Uk[m * nv + v]);   // mirrored: i+3..i-2
     }
-    out[v] = teno6(fp, C.CT) + teno6(fm, C.CT);
+    out[v] = (C.flags & WENO3Z) ? weno3z(fp) + weno3z(fm) : teno6(fp, C.CT) + teno6(fm, C.CT);
   }
   return 1;
 }
@@ -836,6 +854,7 @@ int orc_rhs_tangent(void* h, const double* U, const double* dU, double* T_io, do
 
 // Building blocks exposed for the pins.
 double orc_teno6(const double* f, double CT) { return teno6(f, CT); }
+double orc_weno3z(const double* f) { return weno3z(f); }
 // beta0..beta3, beta6, tau, chi0..chi3, omega0..omega3
 double orc_teno6_detail(const double* f, double CT, double* detail) { return teno6(f, CT, detail); }
 // c_p/R, h/(RT), s/R of species s at temperature T

@@ -66,6 +66,8 @@ def _load():
         L.orc_thermo.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp]
         L.orc_teno6.restype = C.c_double
         L.orc_teno6.argtypes = [_dp, C.c_double]
+        L.orc_weno3z.restype = C.c_double
+        L.orc_weno3z.argtypes = [_dp]
         for f in ("orc_omega22", "orc_omega11"):
             getattr(L, f).restype = C.c_double
             getattr(L, f).argtypes = [C.c_double]
@@ -243,6 +245,12 @@ def omega11(Ts):
 
 def teno6(f, CT=1e-5):
     return _load().orc_teno6(np.ascontiguousarray(f, dtype=np.float64), CT)
+
+
+def weno3z(f):
+    """WENO3-Z reconstruction at x_{i+1/2} from the six-point face stencil
+    f_{i-2..i+3} (it uses f_{i-1}, f_i, f_{i+1})."""
+    return _load().orc_weno3z(np.ascontiguousarray(f, dtype=np.float64))
 
 
 def teno6_detail(f, CT=1e-5):

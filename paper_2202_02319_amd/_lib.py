@@ -12,7 +12,7 @@ HTR_OK, HTR_EINVAL, HTR_ENOMEM, HTR_EDEVICE, HTR_ENONFINITE, HTR_ENEWTON, HTR_ET
 STATUS_NAMES = {0: "HTR_OK", 1: "HTR_EINVAL", 2: "HTR_ENOMEM", 3: "HTR_EDEVICE", 4: "HTR_ENONFINITE",
                 5: "HTR_ENEWTON", 6: "HTR_ETRANGE", 7: "HTR_EUNSUPPORTED"}
 HTR_MAX_NS, HTR_MAX_NR, HTR_MAX_SIDE = 12, 64, 3
-HTR_CHEM_OFF, HTR_VISC_OFF, HTR_FORCE_CENTRAL, HTR_FORCE_TENO = 1, 2, 4, 8
+HTR_CHEM_OFF, HTR_VISC_OFF, HTR_FORCE_CENTRAL, HTR_FORCE_TENO, HTR_WENO3Z = 1, 2, 4, 8, 16
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

@@ -89,6 +89,8 @@ htr_status htr_rhs_adjoint(htr_ctx* c, const double* U, double* T_io, double t, 
                            const double* dlnA_dev, const double* lam, double s, double h, double* Ubar_acc,
                            double* pbar_acc, double* adj_work, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (c->scheme.flags & HTR_WENO3Z)
+    return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (!U || !T_io || !lam || !Ubar_acc || !pbar_acc || !adj_work) return fail(HTR_EINVAL, "NULL pointer");
   if (Ubar_acc == lam || Ubar_acc == U) return fail(HTR_EINVAL, "Ubar_acc must not alias U or lam");
   if (!std::isfinite(t) || !std::isfinite(s) || !std::isfinite(h)) return fail(HTR_EINVAL, "t, s, h must be finite");
@@ -103,6 +105,8 @@ htr_status htr_rk3_step_adjoint(htr_ctx* c, const double* Un, const double* stag
                                 double dt, const htr_laser* laser, const double* dlnA_dev, double Jbar,
                                 double* Ubar, double* pbar_acc, double* adj_work, const void* tape, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (c->scheme.flags & HTR_WENO3Z)
+    return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (!Un || !stages || !T_io || !Ubar || !pbar_acc || !adj_work) return fail(HTR_EINVAL, "NULL pointer");
   if (!std::isfinite(t) || !(dt > 0) || !std::isfinite(Jbar)) return fail(HTR_EINVAL, "need finite t, Jbar and dt > 0");
   htr_status st = check_laser(laser);

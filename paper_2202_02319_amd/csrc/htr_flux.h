@@ -75,6 +75,21 @@ __device__ __forceinline__ void teno6_coeffs(const double f[6], double CT, doubl
   c[5] = w[3] * (1.0 / 12.0);
 }
 
+// Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges) from f_{i-1},
+// f_i, f_{i+1} = f[1..3] of the six-point face stencil: candidates on
+// {i-1, i} and {i, i+1} with optimal weights 1/3 and 2/3, smoothness the
+// squared first differences, global indicator |beta_0 - beta_1|.
+__device__ __forceinline__ double weno3z(const double f[6]) {
+  const double q0 = (-f[1] + 3.0 * f[2]) / 2.0;
+  const double q1 = (f[2] + f[3]) / 2.0;
+  const double b0 = (f[2] - f[1]) * (f[2] - f[1]);
+  const double b1 = (f[3] - f[2]) * (f[3] - f[2]);
+  const double tau = fabs(b0 - b1);
+  const double a0 = (1.0 / 3.0) * (1.0 + tau / (b0 + 1e-40));
+  const double a1 = (2.0 / 3.0) * (1.0 + tau / (b1 + 1e-40));
+  return (a0 * q0 + a1 * q1) / (a0 + a1);
+}
+
 // Cut-off pattern of teno6_core as four bits (bit k: candidate k kept).
 __device__ __forceinline__ unsigned teno6_bits(const double f[6], double CT) {
   double w[4], q[4];

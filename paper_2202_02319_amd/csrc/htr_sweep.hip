@@ -94,7 +94,8 @@ constexpr int APT = (XARM_MAX + BLK - 1) / BLK;
 constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
 
 // Sources plus convective flux differences of every active direction, per
-// cell, into part[nv][N].  The sensor flag, pressure and LF node speed of the
+// cell, into part[nv][N] (TENO6, or WENO3-Z with HTR_WENO3Z, at the faces the
+// hybrid switch marks).  The sensor flag, pressure and LF node speed of the
 // cross are staged once and every face of the tile takes its hybrid decision
 // and Lax-Friedrichs speed once for all variables.  Then, per conserved
 // variable, each staged cell's value and its node flux along each axis are
@@ -348,6 +349,10 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         const double f6 = s_Fn[e0 + mm * bs], u6 = s_U[e0 + mm * bs];
         fp[mm] = 0.5 * (f6 + al * u6);
         fm[5 - mm] = 0.5 * (f6 - al * u6);
+      }
+      if (flags & HTR_WENO3Z) {
+        sF[f] = weno3z(fp) + weno3z(fm);
+        continue;
       }
       double wp[4], qp[4], wm[4], qm[4];
       teno6_core(fp, CT, wp, qp);

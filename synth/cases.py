@@ -32,7 +32,7 @@ RU = 8.31446261815324
 P_ATM = 101325.0
 
 # scheme flags (bit values of the C interfaces)
-CHEM_OFF, VISC_OFF, FORCE_CENTRAL, FORCE_TENO = 1, 2, 4, 8
+CHEM_OFF, VISC_OFF, FORCE_CENTRAL, FORCE_TENO, WENO3Z = 1, 2, 4, 8, 16
 
 
 @dataclass

@@ -33,7 +33,8 @@ def test_header_constants_match_binding():
     hdr = open(os.path.join(os.path.dirname(_lib.HERE), "include", "htr.h")).read()
     for name, val in (("HTR_MAX_NS", 12), ("HTR_MAX_NR", 64), ("HTR_MAX_SIDE", 3)):
         assert re.search(rf"#define {name}\s+{val}\b", hdr)
-    for name, val in (("HTR_CHEM_OFF", 1), ("HTR_VISC_OFF", 2), ("HTR_FORCE_CENTRAL", 4), ("HTR_FORCE_TENO", 8)):
+    for name, val in (("HTR_CHEM_OFF", 1), ("HTR_VISC_OFF", 2), ("HTR_FORCE_CENTRAL", 4), ("HTR_FORCE_TENO", 8),
+                      ("HTR_WENO3Z", 16)):
         assert re.search(rf"#define {name}\s+{val}u", hdr)
 
 

@@ -173,3 +173,16 @@ def test_objective_gradient_against_oracle_tangent():
         Jo, dJo = o.rk3_tangent(U, dU, T, n * prob.dt, prob.dt, las, dth[:4], case.mech.lnA, dth[4:], Jo, dJo)
     assert float(J.item()) == pytest.approx(Jo, rel=1e-9)
     assert float((grad * dth).sum()) == pytest.approx(dJo, rel=1e-9)
+
+
+def test_adjoint_refuses_weno3z():
+    """The discrete adjoint is built for the TENO6 scheme: with WENO3-Z the
+    adjoint entry points return HTR_EUNSUPPORTED before any launch."""
+    case = _case(dict(n=(9, 7, 6), seed=31), synth.WENO3Z)
+    g = htr.Context.from_case(case)
+    U = htr.cons_from_case(g, case)
+    Ubar = torch.zeros_like(U)
+    pbar = torch.zeros(4 + case.mech.nr, dtype=torch.float64, device="cuda")
+    with pytest.raises(htr.HTRError, match="UNSUPPORTED"):
+        htr.htr_rhs_adjoint(g, U, dev(case.T), 0.0, case.laser, None, torch.zeros_like(U), 1.0, 0.0, Ubar, pbar,
+                            htr.new_adjoint_work(g))

@@ -52,7 +52,8 @@ def test_cells_parity(name, kw):
 
 
 @pytest.mark.parametrize("flags", [0, synth.FORCE_CENTRAL, synth.FORCE_TENO, synth.CHEM_OFF,
-                                   synth.VISC_OFF, synth.VISC_OFF | synth.FORCE_TENO])
+                                   synth.VISC_OFF, synth.VISC_OFF | synth.FORCE_TENO,
+                                   synth.WENO3Z, synth.FORCE_TENO | synth.WENO3Z])
 @pytest.mark.parametrize("name,kw", CASES)
 def test_rhs_parity(name, kw, flags):
     case = _case(kw, flags)

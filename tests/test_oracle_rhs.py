@@ -37,7 +37,8 @@ def _case(mech, g, Y, T, p, vel, flags, laser=None):
 
 
 @pytest.mark.parametrize("stretched", [False, True])
-@pytest.mark.parametrize("flags", [synth.CHEM_OFF, synth.CHEM_OFF | synth.FORCE_TENO])
+@pytest.mark.parametrize("flags", [synth.CHEM_OFF, synth.CHEM_OFF | synth.FORCE_TENO,
+                                   synth.CHEM_OFF | synth.FORCE_TENO | synth.WENO3Z])
 def test_free_stream_preservation(stretched, flags):
     n = (7, 6, 5)
     g = synth.stretched_grid(n, 1e-4) if stretched else synth.uniform_grid(n, 1e-4)
@@ -51,9 +52,10 @@ def test_free_stream_preservation(stretched, flags):
     assert np.all(d == 0.0)
 
 
+@pytest.mark.parametrize("scheme", [0, synth.FORCE_TENO, synth.FORCE_TENO | synth.WENO3Z])
 @pytest.mark.parametrize("n", [(9, 7, 6), (12, 1, 1), (8, 10, 1)])
 @pytest.mark.parametrize("stretched", [False, True])
-def test_discrete_conservation(n, stretched):
+def test_discrete_conservation(n, stretched, scheme):
     case = synth.small_case(n=n, ns=4, nr=3, seed=5, stretched=stretched, laser=True)
     case.laser.t0 = 0.0
     o = Oracle(case)
@@ -61,7 +63,7 @@ def test_discrete_conservation(n, stretched):
     T = case.T.copy()
     vol = np.array([o.cell_volume(q) for q in range(case.grid.N)])
     # transport only: every conserved total is stationary
-    o.set_flags(synth.CHEM_OFF)
+    o.set_flags(synth.CHEM_OFF | scheme)
     las_off = synth.Laser()
     d = o.rhs(U, T.copy(), laser=las_off)
     for v in range(o.nv):
@@ -69,7 +71,7 @@ def test_discrete_conservation(n, stretched):
         ref = (vol * np.abs(d[v])).sum()
         assert abs(tot) <= 1e-13 * ref, (v, tot, ref)
     # with chemistry and the laser: total mass and momentum stay, energy gains the deposit
-    o.set_flags(0)
+    o.set_flags(scheme)
     d = o.rhs(U, T.copy())
     qL = o.cells(U, T.copy())[5 + 2 * o.ns + 1]
     mass = (vol * d[:o.ns].sum(axis=0)).sum()
