@@ -119,38 +119,43 @@ def calibration_copy(nbytes=1 << 30):
 
 def cpu_baseline(case, seconds_target=15.0):
     """The oracle (test infrastructure) timed on the host cores on a bounded
-    sample of the same workload: one full right-hand-side evaluation (one
-    stage) of the whole grid, or of a leading slab if that is too long."""
-    import numpy as np
+    sample of the same workload: repeated right-hand-side evaluations (one
+    stage each) of the whole grid, or of a leading slab if one evaluation of
+    the whole grid would take more than the target, for about
+    seconds_target seconds of work."""
     from oracle import Oracle
     import synth
     nz = case.grid.n[2]
-    t_probe = None
-    sub = case
-    for kz in (4, nz):
-        n = (case.grid.n[0], case.grid.n[1], min(kz, nz))
-        g = synth.Grid(n=n, xnode=[case.grid.xnode[0], case.grid.xnode[1], case.grid.xnode[2][:n[2]]],
-                       xin=[case.grid.xin[0], case.grid.xin[1], case.grid.xin[2][:n[2]]],
-                       xif=[case.grid.xif[0], case.grid.xif[1], case.grid.xif[2][:n[2]]], L=case.grid.L)
+    # probe on a 4-layer slab, then size the sample
+    kz = min(4, nz)
+    probe = None
+    while True:
+        n = (case.grid.n[0], case.grid.n[1], kz)
+        g = synth.Grid(n=n, xnode=[case.grid.xnode[0], case.grid.xnode[1], case.grid.xnode[2][:kz]],
+                       xin=[case.grid.xin[0], case.grid.xin[1], case.grid.xin[2][:kz]],
+                       xif=[case.grid.xif[0], case.grid.xif[1], case.grid.xif[2][:kz]], L=case.grid.L)
         N = g.N
         sub = synth.Case(case.name, case.mech, g, case.Y[:, :N], case.T[:N], case.p[:N], case.vel[:, :N],
                          laser=case.laser, flags=case.flags)
         o = Oracle(sub)
         U = o.prim_to_cons()
         T = sub.T.copy()
-        t0 = time.perf_counter()
+        if probe is None:
+            t0 = time.perf_counter()
+            o.rhs(U, T, t=0.0)
+            probe = (time.perf_counter() - t0) / kz        # seconds per z layer
+            kz = nz if probe * nz <= seconds_target else max(1, int(seconds_target / probe))
+            continue
+        break
+    reps = max(1, int(round(seconds_target / (probe * kz))))
+    t0 = time.perf_counter()
+    for _ in range(reps):
         o.rhs(U, T, t=0.0)
-        el = time.perf_counter() - t0
-        if t_probe is None:
-            t_probe = el
-            if el * nz / kz > 2 * seconds_target:
-                break
-        else:
-            break
+    el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": sub.grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one RHS evaluation (one stage) of a {sub.grid.n[0]}x{sub.grid.n[1]}x{sub.grid.n[2]} "
-                      f"slab of the workload, {el:.2f} s"}
+    return {"value": reps * sub.grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} RHS evaluations (one stage each) of a {sub.grid.n[0]}x{sub.grid.n[1]}x{sub.grid.n[2]} "
+                      f"{'grid' if kz == nz else 'slab of the grid'}, {el:.1f} s"}
 
 
 def ensemble_measure(steps, warm=1, sizes=None):
