@@ -292,6 +292,12 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
                                  void* stream);
 /* As htr_check, for the ensemble's status word. */
 htr_status htr_batch_check(htr_batch* b, void* stream);
+/* Per member, the largest value of a packed per-cell field (device [Ntot],
+ * e.g. T_io) into max_dev[m] (device [nmem]); with accumulate != 0,
+ * max_dev[m] = max(max_dev[m], that).  For ensemble workflows such as the
+ * ignition-energy search (Sec. 6: ignition judged by the peak temperature). */
+htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_dev, int accumulate,
+                                void* stream);
 
 /* ------------------------------------------------------------------------
  * Tiles, persistent launches, autotuning.  The flux sweeps work on 256-cell

@@ -92,6 +92,7 @@ def load():
         "htr_batch_work_bytes": (C.c_size_t, [vp]),
         "htr_rk3_steps_batched": (st, [vp, vp, vp, vp, vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
         "htr_batch_check": (st, [vp, vp]),
+        "htr_batch_member_max": (st, [vp, vp, vp, C.c_int, vp]),
         "htr_tile_shape_check": (st, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "htr_set_tiling": (st, [vp, C.POINTER(C.c_int32), C.c_int32]),
         "htr_get_tiling": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),

@@ -157,6 +157,13 @@ htr_status htr_batch_destroy(htr_batch* b) {
   return HTR_OK;
 }
 
+htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_dev, int accumulate,
+                                void* stream) {
+  if (!b || !field || !max_dev) return fail(HTR_EINVAL, "NULL pointer");
+  HIP_OK(launch_member_max(b->dmem, b->nmem, field, max_dev, accumulate, (hipStream_t)stream));
+  return HTR_OK;
+}
+
 int64_t htr_batch_cells(const htr_batch* b, int64_t* offsets) {
   if (!b) return 0;
   if (offsets)

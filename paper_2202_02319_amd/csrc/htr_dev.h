@@ -187,6 +187,8 @@ void default_tile_shape(const int act[3], int shape[3]);
 hipError_t launch_finalize(const Member* mem, int nmem, const double* blkred, double cfl, double* dt_dev,
                            double* J_dev, const double* dt_in, double jcoef, int want_dt, hipStream_t s);
 hipError_t launch_advance_time(int nmem, double* t_dev, const double* dt_dev, hipStream_t s);
+hipError_t launch_member_max(const Member* mem, int nmem, const double* field, double* out, int accumulate,
+                             hipStream_t s);
 // bits (nullable): the forward's TENO cut-off patterns (as launch_conv wrote them).
 hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int ntblocks,
                           const CallArgs& a,

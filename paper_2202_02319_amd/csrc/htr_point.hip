@@ -473,6 +473,26 @@ __global__ __launch_bounds__(BLK) void k_finalize(const Member* __restrict__ mem
   }
 }
 
+// One block per member: the largest value of a packed per-cell field over the
+// member's cells (out[m] = that, or max(out[m], that) when accumulating).
+__global__ __launch_bounds__(BLK) void k_member_max(const Member* __restrict__ mem,
+                                                   const double* __restrict__ field, double* __restrict__ out,
+                                                   int accumulate) {
+  __shared__ double red[BLK / 64];
+  const Member& G = mem[blockIdx.x];
+  double mx = -INFINITY;
+  for (long long q = threadIdx.x; q < G.N; q += BLK) mx = fmax(mx, field[G.off + q]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < BLK / 64; ++w) r = fmax(r, red[w]);
+    out[blockIdx.x] = accumulate ? fmax(out[blockIdx.x], r) : r;
+  }
+}
+
 __global__ void k_advance_time(int nmem, double* __restrict__ t_dev, const double* __restrict__ dt_dev) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < nmem) t_dev[m] += dt_dev[m];
@@ -528,6 +548,12 @@ hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, con
   else
     hipLaunchKernelGGL(k_sensor<false>, dim3(grid), dim3(BLK), 0, s, mem, nmem, nblocks, aux, 7 + ns, flag, grad,
                        theta_c, theta_out, 5 + 2 * ns + 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_member_max(const Member* mem, int nmem, const double* field, double* out, int accumulate,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_member_max, dim3(nmem), dim3(BLK), 0, s, mem, field, out, accumulate);
   return hipGetLastError();
 }
 

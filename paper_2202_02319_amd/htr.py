@@ -349,6 +349,10 @@ def htr_rk3_steps_batched(b, U, T_io, t_dev, dt_dev, compute_dt, nsteps, work, J
                                       _stream(stream)))
 
 
+def htr_batch_member_max(b, field, max_dev, accumulate=False, stream=None):
+    check(b.lib.htr_batch_member_max(b.h, _ptr(field), _ptr(max_dev), int(bool(accumulate)), _stream(stream)))
+
+
 def htr_batch_check(b, stream=None):
     check(b.lib.htr_batch_check(b.h, _stream(stream)))
 

@@ -119,3 +119,21 @@ def test_member_against_oracle(ens):
     rho_c = float(Uo[:o.ns].sum(axis=0).max() * o.cells(Uo, To.copy())[2].max())
     assert normwise_state(Ub, Uo, o.ns, rho_c).max() <= 1e-9
     assert float(host(J)[m]) == pytest.approx(Jo, rel=1e-9)
+
+
+def test_member_max_per_member(ens):
+    """The per-member maximum equals each member's slice maximum (exact: a
+    maximum does not round), and accumulate keeps the larger of the two."""
+    ctx, b, U, T, t, dt, J, work = _batch_setup(ens, dlnA=False)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    f = torch.randn(b.N, generator=g, dtype=torch.float64).cuda()
+    out = torch.empty(b.nmem, dtype=torch.float64, device="cuda")
+    htr.htr_batch_member_max(b, f, out)
+    ref = [float(f[b.offsets[m]:b.offsets[m + 1]].max()) for m in range(b.nmem)]
+    assert host(out).tolist() == ref
+    f2 = f - 0.5
+    f2[b.offsets[2]:b.offsets[3]] += 10.0
+    htr.htr_batch_member_max(b, f2, out, accumulate=True)
+    ref2 = [max(ref[m], float(f2[b.offsets[m]:b.offsets[m + 1]].max())) for m in range(b.nmem)]
+    assert host(out).tolist() == ref2
+    htr.htr_batch_check(b)
