@@ -94,6 +94,15 @@ struct Case {
   double L[3];
   double theta_c, psi_c, CT, cfl;
   unsigned flags;
+  // general curvilinear grid (Sec. 5.2, mapped equations): node coordinates,
+  // the lattice periods, and the metric terms derived from them
+  bool curv = false;
+  std::vector<double> X[3];          // X[c][q]: coordinate c of node q
+  double Pv[3][3];                   // Pv[a]: displacement of the lattice when index a advances by n[a]
+  double Pinv[3][3];                 // inverse of the matrix with columns Pv[a]
+  std::vector<double> mt[9];         // node metric terms (d xi_d / d x_c) / J at mt[3d + c]
+  std::vector<double> mf[9];         // the same at face i+1/2 along d
+  std::vector<double> Jac;           // J = det(d xi / d x) at nodes (1 / index-space cell volume)
   long long N() const { return (long long)n[0] * n[1] * n[2]; }
   long long idx(int i, int j, int k) const { return ((long long)k * n[1] + j) * n[0] + i; }
 };
@@ -324,6 +333,144 @@ static S laser_q(const Case& C, const Params<S>& P, int i, int j, int k, double 
          std::exp(-0.5 * tt * tt);
 }
 
+// ------------------------------------------------------ curvilinear grids
+// Sec. 5.2: the equations are mapped from (x, y, z) to a uniform index space
+// (xi, eta, zeta), with U~ = U/J and F~ = (xi_x F + xi_y G + xi_z H)/J along
+// each index direction, J = det(d xi / d x).  The index spacing is 1.
+//
+// Metric terms.  The paper asks for a free-stream-preserving evaluation; it
+// is taken here in the conservative form of Thomas & Lombard (1979):
+//   (d xi_d / d x_c) / J = D_f[(D_e x_{c1}) x_{c2}] - D_e[(D_f x_{c1}) x_{c2}]
+// with (d, e, f) and (c, c1, c2) cyclic permutations of (0, 1, 2) and D the
+// sixth-order central difference along an index direction (the derivative
+// the six-point central flux implies).  Face values at i+1/2 use the
+// six-point interpolation whose face difference is that same D, so the sum
+// over directions of the face-metric differences is a sum of commuting second
+// differences and vanishes: a uniform flow stays uniform to rounding.
+// Coordinates are taken on the unbounded lattice (a node's image n[a] cells
+// further along a is displaced by Pv[a]) and relative to the node at which
+// the metric is evaluated (the form is invariant under translation).
+static long long floordiv(int i, int n) { return (long long)((i - wrap(i, n)) / n); }
+
+static double lattice_coord(const Case& C, int c, int i, int j, int k) {
+  const int id[3] = {i, j, k};
+  double x = C.X[c][C.idx(wrap(i, C.n[0]), wrap(j, C.n[1]), wrap(k, C.n[2]))];
+  for (int a = 0; a < 3; ++a) x += (double)floordiv(id[a], C.n[a]) * C.Pv[a][c];
+  return x;
+}
+
+// Sixth-order central difference along axis e of f at lattice point p.
+template <class Fn> static double d6(Fn f, const int* p, int e) {
+  const double w[3] = {45.0, -9.0, 1.0};
+  double s = 0;
+  for (int m = 1; m <= 3; ++m) {
+    int pp[3] = {p[0], p[1], p[2]}, pm[3] = {p[0], p[1], p[2]};
+    pp[e] += m;
+    pm[e] -= m;
+    s += w[m - 1] * (f(pp) - f(pm));
+  }
+  return s / 60.0;
+}
+
+static int set_metrics(Case& C) {
+  const long long N = C.N();
+  for (int r = 0; r < 9; ++r) { C.mt[r].assign(N, 0.0); C.mf[r].assign(N, 0.0); }
+  C.Jac.assign(N, 0.0);
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+  for (long long q = 0; q < N; ++q) {
+    const int p0[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+    double x0[3];
+    for (int c = 0; c < 3; ++c) x0[c] = C.X[c][q];
+    auto xr = [&](int c) { return [&, c](const int* p) { return lattice_coord(C, c, p[0], p[1], p[2]) - x0[c]; }; };
+    for (int d = 0; d < 3; ++d) {
+      const int e = (d + 1) % 3, f = (d + 2) % 3;
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        auto xc1 = xr(c1), xc2 = xr(c2);
+        auto ge = [&](const int* p) { return d6(xc1, p, e) * xc2(p); };   // (D_e x_c1) x_c2
+        auto gf = [&](const int* p) { return d6(xc1, p, f) * xc2(p); };   // (D_f x_c1) x_c2
+        C.mt[3 * d + c][q] = d6(ge, p0, f) - d6(gf, p0, e);
+      }
+    }
+    // 1/J = det(d x / d xi): columns D_e x
+    double A[3][3];
+    for (int c = 0; c < 3; ++c)
+      for (int e = 0; e < 3; ++e) A[c][e] = d6(xr(c), p0, e);
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(det > 0) || !std::isfinite(det)) { bad += 1; continue; }
+    C.Jac[q] = 1.0 / det;
+  }
+  if (bad) return EINVAL;
+  // face values: six-point interpolation along d of the node values
+  const double cw[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+  for (int d = 0; d < 3; ++d)
+    for (long long q = 0; q < N; ++q) {
+      int c0[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int m = 0; m < 6; ++m) {
+          int cc[3] = {c0[0], c0[1], c0[2]};
+          cc[d] = wrap(c0[d] - 2 + m, C.n[d]);
+          s += cw[m] * C.mt[3 * d + c][C.idx(cc[0], cc[1], cc[2])];
+        }
+        C.mf[3 * d + c][q] = s / 60.0;
+      }
+    }
+  return OK;
+}
+
+// Laser kernel on a curvilinear grid: the same Gaussian of the distance to
+// the centre, summed over the lattice images.  The offset is first reduced
+// to the nearest image in lattice coordinates (a discrete choice); images
+// up to M_a periods away along each active axis are summed, with M_a such
+// that every omitted image lies beyond 9.103 sigma_r (the distance between
+// lattice planes along a is det / |Pv[b] x Pv[c]|).  An inactive axis drops
+// its coordinate, as on rectilinear grids.
+template <class S>
+static S laser_q_curv(const Case& C, const Params<S>& P, long long q, double t) {
+  if (!P.on) return S(0);
+  int d = 0, act[3];
+  for (int a = 0; a < 3; ++a) { act[a] = C.n[a] > 1; d += act[a]; }
+  S r[3], sl[3];
+  for (int c = 0; c < 3; ++c) r[c] = C.X[c][q] - P.xc[c];
+  for (int a = 0; a < 3; ++a) {
+    sl[a] = C.Pinv[a][0] * r[0] + C.Pinv[a][1] * r[1] + C.Pinv[a][2] * r[2];
+    if (act[a]) sl[a] = sl[a] - std::nearbyint(val(sl[a]));
+    else sl[a] = S(0);
+  }
+  S rm[3];
+  for (int c = 0; c < 3; ++c) rm[c] = sl[0] * C.Pv[0][c] + sl[1] * C.Pv[1][c] + sl[2] * C.Pv[2][c];
+  double vol = std::fabs(C.Pv[0][0] * (C.Pv[1][1] * C.Pv[2][2] - C.Pv[1][2] * C.Pv[2][1]) -
+                         C.Pv[0][1] * (C.Pv[1][0] * C.Pv[2][2] - C.Pv[1][2] * C.Pv[2][0]) +
+                         C.Pv[0][2] * (C.Pv[1][0] * C.Pv[2][1] - C.Pv[1][1] * C.Pv[2][0]));
+  int M[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    if (!act[a]) continue;
+    const double* u = C.Pv[(a + 1) % 3];
+    const double* w = C.Pv[(a + 2) % 3];
+    double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    double h = vol / std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    M[a] = std::max(0, (int)std::ceil(9.103 * P.sr / h - 0.5));
+  }
+  S g = 0;
+  for (int m0 = -M[0]; m0 <= M[0]; ++m0)
+    for (int m1 = -M[1]; m1 <= M[1]; ++m1)
+      for (int m2 = -M[2]; m2 <= M[2]; ++m2) {
+        S r2 = 0;
+        for (int c = 0; c < 3; ++c) {
+          S z = rm[c] - (m0 * C.Pv[0][c] + m1 * C.Pv[1][c] + m2 * C.Pv[2][c]);
+          r2 += z * z;
+        }
+        g += exp(-0.5 * r2 / (P.sr * P.sr));
+      }
+  double norm = std::pow(2.0 * PI, 0.5 * (d + 1)) * std::pow(P.sr, d) * P.st;
+  double tt = (t - P.t0) / P.st;
+  return P.E / norm * g * std::exp(-0.5 * tt * tt);
+}
+
 // ----------------------------------------------------------------- WENO3-Z
 // Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges 2013), the
 // paper's alternative shock-capturing scheme (Sec. 5.2), from f_{i-1}, f_i,
@@ -418,7 +565,7 @@ static int eval_cells(const Case& C, const Params<S>& P, const S* U, double* T_i
     if (!(C.flags & CHEM_OFF)) chemistry(C, P, Uc.data(), z);
     else z.hrr = 0;
     int i = q % C.n[0], j = (q / C.n[0]) % C.n[1], k = q / ((long long)C.n[0] * C.n[1]);
-    z.qL = laser_q(C, P, i, j, k, t);
+    z.qL = C.curv ? laser_q_curv(C, P, q, t) : laser_q(C, P, i, j, k, t);
   }
   if (err) return err;
   for (long long q = 0; q < N; ++q) T_io[q] = val(F.cell[q].T);
@@ -436,6 +583,13 @@ static int eval_cells(const Case& C, const Params<S>& P, const S* U, double* T_i
       cm[a] = wrap(c[a] - 1, C.n[a]);
       const Cell<S>& zp = F.cell[C.idx(cp[0], cp[1], cp[2])];
       const Cell<S>& zm = F.cell[C.idx(cm[0], cm[1], cm[2])];
+      if (C.curv) {
+        // chain rule: d/dx_b = sum_a (d xi_a / d x_b) d/d xi_a, with d xi_a / d x_b = J mt[3a + b]
+        for (int b = 0; b < 3; ++b)
+          for (int m = 0; m < 3; ++m)
+            g[b][m] += C.Jac[q] * C.mt[3 * a + b][q] * (val(zp.u[m]) - val(zm.u[m])) / 2.0;
+        continue;
+      }
       for (int m = 0; m < 3; ++m) g[a][m] = C.xin[a][c[a]] * (val(zp.u[m]) - val(zm.u[m])) / 2.0;
     }
     double div = g[0][0] + g[1][1] + g[2][2];
@@ -571,6 +725,151 @@ static void diff_flux(const Case& C, const Fields<S>& F, int d, int i, int j, in
   out[ns + 3] = work - qn;
 }
 
+// Mapped convective flux of variable v at a node through a face with metric
+// vector n = (d xi_d / d x) / J: the physical flux projected on n.
+template <class S>
+static S node_flux_mapped(const Case& C, const S* Uc, const Cell<S>& z, int v, const double* n) {
+  const int ns = C.ns;
+  S un = z.u[0] * n[0] + z.u[1] * n[1] + z.u[2] * n[2];
+  if (v < ns) return Uc[v] * un;
+  if (v < ns + 3) return Uc[v] * un + z.p * n[v - ns];
+  return (Uc[v] + z.p) * un;
+}
+
+// Step 3b on a curvilinear grid: the same hybrid switch, central flux and
+// TENO6 (or WENO3-Z) on the local Lax-Friedrichs split, applied to the mapped
+// flux with the face's metric vector held fixed across the stencil; the LF
+// speed is the largest |u . n| + c |n| over the stencil.
+template <class S>
+static int conv_flux_curv(const Case& C, const S* U, const Fields<S>& F, int d, long long qf, const long long* st,
+                          S* out) {
+  const long long N = C.N();
+  const int nv = C.ns + 4;
+  double n[3] = {C.mf[3 * d][qf], C.mf[3 * d + 1][qf], C.mf[3 * d + 2][qf]};
+  double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  bool teno = use_teno(C, F, st);
+  std::vector<S> Uk(nv * 6);
+  for (int m = 0; m < 6; ++m)
+    for (int v = 0; v < nv; ++v) Uk[m * nv + v] = U[v * N + st[m]];
+  if (!teno) {
+    const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+    for (int v = 0; v < nv; ++v) {
+      S s = 0;
+      for (int m = 0; m < 6; ++m) s += cc[m] * node_flux_mapped(C, &Uk[m * nv], F.cell[st[m]], v, n);
+      out[v] = s / 60.0;
+    }
+    return 0;
+  }
+  int am = 0;
+  double best = -1;
+  for (int m = 0; m < 6; ++m) {
+    const Cell<S>& z = F.cell[st[m]];
+    double sp = std::fabs(val(z.u[0]) * n[0] + val(z.u[1]) * n[1] + val(z.u[2]) * n[2]) + val(z.c) * nn;
+    if (sp > best) { best = sp; am = m; }
+  }
+  const Cell<S>& za = F.cell[st[am]];
+  S alpha = fabs(za.u[0] * n[0] + za.u[1] * n[1] + za.u[2] * n[2]) + za.c * nn;
+  for (int v = 0; v < nv; ++v) {
+    S fp[6], fm[6];
+    for (int m = 0; m < 6; ++m) {
+      S fl = node_flux_mapped(C, &Uk[m * nv], F.cell[st[m]], v, n);
+      fp[m] = 0.5 * (fl + alpha * Uk[m * nv + v]);
+      fm[5 - m] = 0.5 * (fl - alpha * Uk[m * nv + v]);
+    }
+    out[v] = (C.flags & WENO3Z) ? weno3z(fp) + weno3z(fm) : teno6(fp, C.CT) + teno6(fm, C.CT);
+  }
+  return 1;
+}
+
+// Step 3c on a curvilinear grid: the mapped diffusive flux through face
+// i+1/2 along d.  Index-space derivatives at the face: along d from the two
+// adjacent nodes, along the other active axes the mean of the two nodes'
+// central differences (the second-order compact face form of the rectilinear
+// case).  Physical gradients by the chain rule with the face value of
+// d xi_e / d x (mean of the two nodes); the flux vector is then projected on
+// the face metric vector, as the convective flux.  Face coefficients are
+// arithmetic means.
+template <class S>
+static void diff_flux_curv(const Case& C, const Fields<S>& F, int d, int i, int j, int k, S* out) {
+  const int ns = C.ns;
+  int c0[3] = {i, j, k}, c1[3] = {i, j, k};
+  c1[d] = wrap(c0[d] + 1, C.n[d]);
+  const long long qa = C.idx(c0[0], c0[1], c0[2]), qb = C.idx(c1[0], c1[1], c1[2]);
+  const Cell<S>& A = F.cell[qa];
+  const Cell<S>& B = F.cell[qb];
+  const double n[3] = {C.mf[3 * d][qa], C.mf[3 * d + 1][qa], C.mf[3 * d + 2][qa]};
+  // G[e][b] = d xi_e / d x_b at the face
+  double G[3][3];
+  for (int e = 0; e < 3; ++e)
+    for (int b = 0; b < 3; ++b)
+      G[e][b] = 0.5 * (C.Jac[qa] * C.mt[3 * e + b][qa] + C.Jac[qb] * C.mt[3 * e + b][qb]);
+  // index-space derivative along e at the face of a per-cell quantity
+  auto dxi = [&](auto get, int e) -> S {
+    if (e == d) return get(B) - get(A);
+    if (C.n[e] == 1) return S(0);
+    S s = 0;
+    for (int side = 0; side < 2; ++side) {
+      const int* c = side ? c1 : c0;
+      int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+      cp[e] = wrap(c[e] + 1, C.n[e]);
+      cm[e] = wrap(c[e] - 1, C.n[e]);
+      s += 0.5 * (get(F.cell[C.idx(cp[0], cp[1], cp[2])]) - get(F.cell[C.idx(cm[0], cm[1], cm[2])])) / 2.0;
+    }
+    return s;
+  };
+  // physical gradient at the face
+  auto grad = [&](auto get, S* g) {
+    S de[3];
+    for (int e = 0; e < 3; ++e) de[e] = dxi(get, e);
+    for (int b = 0; b < 3; ++b) g[b] = G[0][b] * de[0] + G[1][b] * de[1] + G[2][b] * de[2];
+  };
+  S gu[3][3];   // gu[b][m] = d u_m / d x_b
+  for (int m = 0; m < 3; ++m) {
+    S g[3];
+    grad([m](const Cell<S>& z) { return z.u[m]; }, g);
+    for (int b = 0; b < 3; ++b) gu[b][m] = g[b];
+  }
+  S mu = 0.5 * (A.mu + B.mu), lam = 0.5 * (A.lam + B.lam), rho = 0.5 * (A.rho + B.rho);
+  S W = 0.5 * (A.W + B.W);
+  S divu = gu[0][0] + gu[1][1] + gu[2][2];
+  // (tau . n)_m = sum_b n_b tau_{b m}, Stokes hypothesis
+  S tn[3];
+  for (int m = 0; m < 3; ++m) {
+    tn[m] = 0;
+    for (int b = 0; b < 3; ++b) {
+      S tau = mu * (gu[b][m] + gu[m][b]);
+      if (b == m) tau -= (2.0 / 3.0) * mu * divu;
+      tn[m] += n[b] * tau;
+    }
+  }
+  std::vector<S> Jn(ns), Yf(ns), hf(ns);
+  S corr = 0;
+  for (int s = 0; s < ns; ++s) {
+    S g[3];
+    grad([s](const Cell<S>& z) { return z.X[s]; }, g);
+    S dXn = g[0] * n[0] + g[1] * n[1] + g[2] * n[2];
+    S Df = 0.5 * (A.D[s] + B.D[s]);
+    Jn[s] = -rho * Df * (C.W[s] / W) * dXn;
+    corr += rho * Df * (C.W[s] / W) * dXn;
+    Yf[s] = 0.5 * (A.Y[s] + B.Y[s]);
+    hf[s] = 0.5 * (A.h[s] + B.h[s]);
+  }
+  S gT[3];
+  grad([](const Cell<S>& z) { return z.T; }, gT);
+  S qn = -lam * (gT[0] * n[0] + gT[1] * n[1] + gT[2] * n[2]);
+  for (int s = 0; s < ns; ++s) {
+    Jn[s] += Yf[s] * corr;
+    qn += Jn[s] * hf[s];
+  }
+  for (int s = 0; s < ns; ++s) out[s] = -Jn[s];
+  S work = 0;
+  for (int m = 0; m < 3; ++m) {
+    out[ns + m] = tn[m];
+    work += tn[m] * 0.5 * (A.u[m] + B.u[m]);
+  }
+  out[ns + 3] = work - qn;
+}
+
 template <class S>
 static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, double t, S* dUdt,
                S* hrr_out, unsigned char* mask, Fields<S>* keep) {
@@ -602,19 +901,21 @@ static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, doub
         st[m] = C.idx(cc[0], cc[1], cc[2]);
       }
       std::vector<S> fc(nv), fd(nv);
-      int te = conv_flux(C, U, F, d, st, fc.data());
+      int te = C.curv ? conv_flux_curv(C, U, F, d, q, st, fc.data()) : conv_flux(C, U, F, d, st, fc.data());
       if (mask) mask[(size_t)d * N + q] = (unsigned char)te;
-      if (!(C.flags & VISC_OFF)) diff_flux(C, F, d, c[0], c[1], c[2], fd.data());
-      else for (int v = 0; v < nv; ++v) fd[v] = 0;
+      if (C.flags & VISC_OFF) for (int v = 0; v < nv; ++v) fd[v] = 0;
+      else if (C.curv) diff_flux_curv(C, F, d, c[0], c[1], c[2], fd.data());
+      else diff_flux(C, F, d, c[0], c[1], c[2], fd.data());
       for (int v = 0; v < nv; ++v) { Fc[(size_t)q * nv + v] = fc[v]; Fd[(size_t)q * nv + v] = fd[v]; }
     }
-    // flux differences: dU/dt += xi_d (-(Fc_{i+1/2} - Fc_{i-1/2}) + (Fd_{i+1/2} - Fd_{i-1/2}))
+    // flux differences: dU/dt += xi_d (-(Fc_{i+1/2} - Fc_{i-1/2}) + (Fd_{i+1/2} - Fd_{i-1/2})),
+    // on a curvilinear grid J times the mapped flux difference (index spacing 1)
     for (long long q = 0; q < N; ++q) {
       int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
       int cm[3] = {c[0], c[1], c[2]};
       cm[d] = wrap(c[d] - 1, C.n[d]);
       long long qm = C.idx(cm[0], cm[1], cm[2]);
-      double xi = C.xin[d][c[d]];
+      double xi = C.curv ? C.Jac[q] : C.xin[d][c[d]];
       for (int v = 0; v < nv; ++v) {
         S conv = Fc[(size_t)q * nv + v] - Fc[(size_t)qm * nv + v];
         S dif = Fd[(size_t)q * nv + v] - Fd[(size_t)qm * nv + v];
@@ -627,6 +928,7 @@ static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, doub
 
 // Cell volume (product of widths along all three axes).
 static double cell_volume(const Case& C, long long q) {
+  if (C.curv) return 1.0 / C.Jac[q];
   int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
   return 1.0 / (C.xin[0][c[0]] * C.xin[1][c[1]] * C.xin[2][c[2]]);
 }
@@ -646,6 +948,18 @@ static int stable_dt(const Case& C, const double* U, double* T_io, double* dt) {
     double sc = 0, sd = 0;
     for (int a = 0; a < 3; ++a) {
       if (C.n[a] == 1) continue;
+      if (C.curv) {
+        // contravariant speed |u . grad xi_a| + c |grad xi_a|, grad xi_a = J mt_a
+        double g[3], un = 0, g2 = 0;
+        for (int b = 0; b < 3; ++b) {
+          g[b] = C.Jac[q] * C.mt[3 * a + b][q];
+          un += z.u[b] * g[b];
+          g2 += g[b] * g[b];
+        }
+        sc += std::fabs(un) + z.c * std::sqrt(g2);
+        sd += g2;
+        continue;
+      }
       double xi = C.xin[a][c[a]];
       sc += (std::fabs(z.u[a]) + z.c) * xi;
       sd += xi * xi;
@@ -725,6 +1039,54 @@ void* orc_case_new(int ns, int nr, const double* W, const double* a7, const doub
 }
 
 void orc_case_free(void* h) { delete (Case*)h; }
+
+// Makes the case curvilinear: node coordinates xyz[3][N] and lattice periods
+// P[3][3] (row a: the displacement along index a over n[a] cells).  An
+// inactive axis must have its period along its own coordinate axis, and the
+// other periods no component along it.  Returns 1 for an invalid lattice or
+// a node with det(d x / d xi) <= 0.
+int orc_case_set_curvilinear(void* h, const double* xyz, const double* P) {
+  Case& C = *(Case*)h;
+  const long long N = C.N();
+  for (int c = 0; c < 3; ++c) C.X[c].assign(xyz + c * N, xyz + (c + 1) * N);
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) C.Pv[a][c] = P[3 * a + c];
+  for (int a = 0; a < 3; ++a) {
+    if (C.n[a] > 1) continue;
+    for (int c = 0; c < 3; ++c)
+      if (c != a && C.Pv[a][c] != 0.0) return EINVAL;
+    for (int b = 0; b < 3; ++b)
+      if (b != a && C.Pv[b][a] != 0.0) return EINVAL;
+    if (!(C.Pv[a][a] != 0.0)) return EINVAL;
+  }
+  // inverse of the matrix whose columns are the periods (cofactors / det)
+  double B[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int a = 0; a < 3; ++a) B[r][a] = C.Pv[a][r];
+  double det = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+               B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+  if (!(std::fabs(det) > 0)) return EINVAL;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+      C.Pinv[r][c] = (B[r1][c1] * B[r2][c2] - B[r1][c2] * B[r2][c1]) / det;
+    }
+  C.curv = true;
+  return set_metrics(C);
+}
+
+// Node metric terms [9][N] ((d xi_d / d x_c) / J at row 3d + c), face metric
+// terms [9][N], and J [N] of a curvilinear case.
+void orc_metrics(void* h, double* mt, double* mf, double* jac) {
+  const Case& C = *(Case*)h;
+  const long long N = C.N();
+  for (int r = 0; r < 9; ++r)
+    for (long long q = 0; q < N; ++q) {
+      mt[r * N + q] = C.mt[r][q];
+      mf[r * N + q] = C.mf[r][q];
+    }
+  for (long long q = 0; q < N; ++q) jac[q] = C.Jac[q];
+}
 
 void orc_set_flags(void* h, unsigned flags) { ((Case*)h)->flags = flags; }
 

@@ -50,6 +50,8 @@ def _load():
                                    C.c_double, _ip, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_uint]
         L.orc_case_free.argtypes = [C.c_void_p]
+        L.orc_case_set_curvilinear.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_metrics.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_set_flags.argtypes = [C.c_void_p, C.c_uint]
         L.orc_prim_to_cons.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
         L.orc_cells.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp]
@@ -112,12 +114,21 @@ class Oracle:
         nr_ = np.ascontiguousarray(m.nu_r.astype(np.int32).reshape(-1)) if m.nr else np.zeros(1, np.int32)
         self._keep += [nf, nr_]
         z1 = lambda a: f64(a) if len(a) else f64(np.zeros(1))  # noqa: E731
+        self.curv = hasattr(g, "xyz")
+        if self.curv:   # the rectilinear arrays are unused placeholders
+            ones = f64(np.ones(int(sum(g.n))))
+            xn, xi, xf, Lp = f64(np.zeros(int(sum(g.n)))), ones, ones, f64(np.ones(3))
+        else:
+            xn, xi, xf = f64(np.concatenate(g.xnode)), f64(np.concatenate(g.xin)), f64(np.concatenate(g.xif))
+            Lp = f64(np.array(g.L))
         self.h = L.orc_case_new(
             m.ns, m.nr, f64(m.W), f64(m.nasa7.reshape(-1)), f64(m.lj_sigma), f64(m.lj_epsk), z1(m.lnA),
             z1(m.beta), z1(m.Ea), nf, nr_, float(m.Tmin), float(m.Tmax), np.array(g.n, np.int32),
-            f64(np.concatenate(g.xnode)), f64(np.concatenate(g.xin)), f64(np.concatenate(g.xif)),
-            f64(np.array(g.L)), float(case.theta_c), float(case.psi_c), float(case.teno_CT), float(case.cfl),
+            xn, xi, xf, Lp, float(case.theta_c), float(case.psi_c), float(case.teno_CT), float(case.cfl),
             int(self.flags))
+        if self.curv:
+            _chk(L.orc_case_set_curvilinear(self.h, f64(np.asarray(g.xyz).reshape(-1)),
+                                            f64(np.asarray(g.period).reshape(-1))))
         self.case = case
 
     def __del__(self):
@@ -214,6 +225,13 @@ class Oracle:
                                     self._las(laser), np.ascontiguousarray(np.asarray(dlas, float)), _ptr(dlnA),
                                     dUdt, ddUdt, hrr, dhrr))
         return dUdt, ddUdt, hrr, dhrr
+
+    def metrics(self):
+        """Curvilinear grids: node metric terms [3][3][N] ((d xi_d / d x_c) / J
+        at [d][c]), the same at faces i+1/2 along d, and J [N]."""
+        mt, mf, jac = np.zeros((9, self.N)), np.zeros((9, self.N)), np.zeros(self.N)
+        self.L.orc_metrics(self.h, mt, mf, jac)
+        return mt.reshape(3, 3, self.N), mf.reshape(3, 3, self.N), jac
 
     def cell_volume(self, q):
         return self.L.orc_cell_volume(self.h, int(q))

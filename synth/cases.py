@@ -92,6 +92,106 @@ def stretched_grid(n, d, amp=0.2) -> Grid:
 
 
 @dataclass
+class CurvGrid:
+    """General curvilinear periodic grid: node coordinates xyz[3][N] (x
+    fastest, then y, then z) and the lattice periods period[3][3] (row a: the
+    displacement of the node lattice when index a advances by n[a])."""
+    n: tuple
+    xyz: np.ndarray
+    period: np.ndarray
+
+    @property
+    def N(self):
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def L(self):
+        return tuple(float(np.linalg.norm(self.period[a])) for a in range(3))
+
+    def mesh(self):
+        """Node coordinates, each shaped [nz][ny][nx]."""
+        sh = (self.n[2], self.n[1], self.n[0])
+        return tuple(self.xyz[c].reshape(sh) for c in range(3))
+
+
+def as_curvilinear(g: Grid) -> CurvGrid:
+    """A rectilinear grid written as a curvilinear one (same nodes)."""
+    x, y, z = g.mesh()
+    return CurvGrid(n=g.n, xyz=np.stack([x.ravel(), y.ravel(), z.ravel()]), period=np.diag(np.array(g.L, float)))
+
+
+def affine_grid(n, d, A, origin=(0.0, 0.0, 0.0)) -> CurvGrid:
+    """Uniform lattice mapped by the matrix A: node (i, j, k) at
+    origin + A ((i + 1/2) d_x, (j + 1/2) d_y, (k + 1/2) d_z); periods A L_a e_a.
+    A rotation gives a rotated Cartesian grid, a shear a skewed one."""
+    g = uniform_grid(n, d)
+    x, y, z = g.mesh()
+    A = np.asarray(A, float)
+    P = np.stack([x.ravel(), y.ravel(), z.ravel()])
+    return CurvGrid(n=g.n, xyz=A @ P + np.asarray(origin, float)[:, None],
+                    period=np.stack([A @ (g.L[a] * np.eye(3)[a]) for a in range(3)]))
+
+
+def rotation(ax, ay, az):
+    """Rotation matrix R_z(az) R_y(ay) R_x(ax)."""
+    cx, sx, cy, sy, cz, sz = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+def skewed_grid(n, d, beta=0.2, origin=None) -> CurvGrid:
+    """Periodic skewed grid of the paper's convergence tests (Sec. 5.3.1):
+    each coordinate is displaced by beta L/2 times the sine of the other
+    active coordinates (averaged over them),
+        x_c = xi_c + beta (L_c / 2) mean_{c' != c} sin(2 pi xi_c' / L_c'),
+    with xi the uniform lattice position.  In 2-D this is
+    x = xi + beta (L/2) sin(2 pi eta / L), y = eta + beta (L/2) sin(2 pi xi / L),
+    a periodic counterpart of the printed map, whose displacement is also
+    beta L/2 at most; the grid lines turn by up to atan(beta pi) (32 degrees
+    at beta = 0.2; half that slope per term in 3-D)."""
+    g = uniform_grid(n, d)
+    x, y, z = g.mesh()
+    xi = [x, y, z]
+    act = [a for a in range(3) if g.n[a] > 1]
+    out = []
+    for c in range(3):
+        v = xi[c].copy()
+        others = [a for a in act if a != c]
+        if c in act and others:
+            v = v + beta * g.L[c] / 2 * sum(np.sin(2 * np.pi * xi[a] / g.L[a]) for a in others) / len(others)
+        out.append(v.ravel())
+    xyz = np.stack(out)
+    if origin is not None:
+        xyz = xyz + np.asarray(origin, float)[:, None]
+    return CurvGrid(n=g.n, xyz=xyz, period=np.diag(np.array(g.L, float)))
+
+
+def wavy_grid(n, d, amp=0.25, seed=0) -> CurvGrid:
+    """Periodic wavy grid: each coordinate displaced by amp cells times a
+    product of sines of all active lattice coordinates with seeded phases,
+        x_c = xi_c + amp d_c prod_a sin(2 pi xi_a / L_a + phi_ca),
+    so that every metric term varies along every axis (no separable
+    structure for the metric differences to cancel on)."""
+    g = uniform_grid(n, d)
+    x, y, z = g.mesh()
+    xi = [x, y, z]
+    act = [a for a in range(3) if g.n[a] > 1]
+    ph = np.random.default_rng(seed).uniform(0, 2 * np.pi, size=(3, 3))
+    out = []
+    for c in range(3):
+        v = xi[c].copy()
+        if c in act:
+            w = np.ones_like(v)
+            for a in act:
+                w = w * np.sin(2 * np.pi * xi[a] / g.L[a] + ph[c, a])
+            v = v + amp * g.spacing()[c] * g.n[c] / (2 * np.pi) * w
+        out.append(v.ravel())
+    return CurvGrid(n=g.n, xyz=np.stack(out), period=np.diag(np.array(g.L, float)))
+
+
+@dataclass
 class Laser:
     """Gaussian deposition kernel (Sec. 6.3.1): energy, centre, spatial and
     temporal support, delay."""
@@ -326,6 +426,14 @@ def vortex_case(n=32, L=10.0) -> Case:
     x = x[0] - L / 2
     y = y[0] - L / 2
     return _vortex_fields(mech, g, x, y)
+
+
+def vortex_case_curv(grid: CurvGrid, L=10.0) -> Case:
+    """The isentropic vortex of vortex_case on a curvilinear grid spanning
+    [0, L]^2 (fields at the physical node coordinates, centred at L/2)."""
+    mech = single_species(RU, 3.5, Tmin=1e-3, Tmax=1e3)
+    x, y, _ = grid.mesh()
+    return _vortex_fields(mech, grid, x[0] - L / 2, y[0] - L / 2)
 
 
 def vortex_exact(x, y, t=0.0, beta=5.0, alpha=0.5, r0=0.5, gamma=1.4, u0=1.0, v0=1.0, T0=1.0, L=10.0):

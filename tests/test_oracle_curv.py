@@ -1,0 +1,243 @@
+"""Pins of the oracle on general curvilinear grids (paper Sec. 5.2, the
+mapped equations with U~ = U/J and F~ = (xi_x F + xi_y G + xi_z H)/J; the
+convergence set-up of Sec. 5.3.1 on a skewed grid).
+
+- the metric terms equal the closed-form cofactors of an affine map exactly,
+  and converge at sixth order to the analytic ones of a smooth map;
+- a uniform flow stays uniform on a skewed grid (free-stream preservation);
+- a rectilinear grid written as a curvilinear one gives the rectilinear
+  right-hand side, time step and per-cell fields;
+- on a rotated lattice the central-scheme right-hand side is the rotated
+  Cartesian one (scalars equal, momentum rotated): this fixes every index
+  and transpose of the metric terms, the projected fluxes, the chain rule of
+  the diffusive fluxes and the laser's lattice images;
+- the flux differences conserve sum (1/J) U;
+- the laser kernel on a sheared lattice integrates to E;
+- the isentropic vortex converges at high order on the skewed grid.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle
+
+FLAG_SETS = [0, synth.FORCE_TENO, synth.FORCE_TENO | synth.WENO3Z, synth.FORCE_CENTRAL]
+
+
+def _curv_case(c, grid, **kw):
+    """The same fields on another grid with the same node count."""
+    args = dict(laser=c.laser, flags=c.flags)
+    args.update(kw)
+    return synth.Case(c.name, c.mech, grid, c.Y, c.T, c.p, c.vel, **args)
+
+
+def _cofactors(A):
+    """Rows: (d xi_d / d x) / J for x = A xi, i.e. det(A) inv(A)."""
+    return np.linalg.det(A) * np.linalg.inv(A)
+
+
+@pytest.mark.parametrize("n", [(8, 7, 6), (9, 8, 1)])
+def test_metrics_of_an_affine_map_are_its_cofactors(n):
+    rng = np.random.default_rng(3)
+    d = (1e-4, 1.3e-4, 0.8e-4)
+    A = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+    if n[2] == 1:   # an inactive axis keeps its own direction
+        A[2, :2] = A[:2, 2] = 0.0
+        A[2, 2] = 1.0
+    g = synth.affine_grid(n, d, A, origin=(0.3e-3, -0.2e-3, 0.1e-3))
+    mech = synth.make_mechanism(3, 1, 2)
+    N = g.N
+    o = Oracle(synth.Case("a", mech, g, np.full((3, N), 1 / 3), np.full(N, 500.0), np.full(N, 1e5),
+                          np.zeros((3, N))))
+    mt, mf, jac = o.metrics()
+    Ad = A * np.array(d)[None, :]           # d x / d(index)
+    ref = _cofactors(Ad)
+    for dd in range(3):
+        for c in range(3):
+            scale = np.abs(ref).max()
+            assert np.abs(mt[dd, c] - ref[dd, c]).max() < 1e-12 * scale
+            assert np.abs(mf[dd, c] - ref[dd, c]).max() < 1e-12 * scale
+    assert np.allclose(jac, 1 / np.linalg.det(Ad), rtol=1e-12, atol=0)
+
+
+def test_metrics_converge_at_sixth_order():
+    """On the smooth skewed map the node metrics approach the analytic
+    cofactors of d x / d(index) at sixth order."""
+    errs = []
+    for m in (16, 32):
+        n = (m, m, m)
+        dx = 1.0 / m
+        g = synth.skewed_grid(n, dx, beta=0.2)
+        mech = synth.make_mechanism(3, 1, 2)
+        N = g.N
+        o = Oracle(synth.Case("s", mech, g, np.full((3, N), 1 / 3), np.full(N, 500.0), np.full(N, 1e5),
+                              np.zeros((3, N))))
+        mt, _, jac = o.metrics()
+        # analytic d x_c / d xi_a for the map of skewed_grid (L = 1, mean over the other two axes)
+        x, y, z = synth.uniform_grid(n, dx).mesh()
+        xi = [x.ravel(), y.ravel(), z.ravel()]
+        err = 0.0
+        for q in range(0, N, 7):
+            Jm = np.eye(3)
+            for c in range(3):
+                for a in range(3):
+                    if a != c:
+                        Jm[c, a] = 0.2 / 2 * 2 * np.pi * np.cos(2 * np.pi * xi[a][q]) / 2
+            Ad = Jm * dx
+            ref = _cofactors(Ad)
+            err = max(err, np.abs(mt[:, :, q] - ref).max() / np.abs(ref).max())
+            err = max(err, abs(jac[q] * np.linalg.det(Ad) - 1))
+        errs.append(err)
+    order = np.log2(errs[0] / errs[1])
+    assert order > 5.5, (errs, order)
+
+
+def _grid(kind, n, d):
+    return synth.skewed_grid(n, d, beta=0.2) if kind == "skewed" else synth.wavy_grid(n, d, amp=0.25, seed=4)
+
+
+@pytest.mark.parametrize("flags", [synth.CHEM_OFF | f for f in FLAG_SETS])
+@pytest.mark.parametrize("n", [(10, 9, 8), (12, 10, 1)])
+@pytest.mark.parametrize("kind", ["skewed", "wavy"])
+def test_free_stream_preserved_on_a_skewed_grid(kind, n, flags):
+    """The wavy grid's metric terms vary along every axis, so a face metric
+    that is not the matching interpolation of the node metrics fails here."""
+    g = _grid(kind, n, 1e-4)
+    mech = synth.make_mechanism(5, 4, 3)
+    N = g.N
+    Y = np.repeat(np.array([0.1, 0.2, 0.3, 0.15, 0.25])[:, None], N, axis=1)
+    vel = np.array([120.0, -80.0, 45.0 if n[2] > 1 else 0.0])[:, None] * np.ones(N)
+    o = Oracle(synth.Case("fs", mech, g, Y, np.full(N, 900.0), np.full(N, 2e5), vel, flags=flags))
+    U = o.prim_to_cons()
+    d = o.rhs(U, np.full(N, 900.0))
+    mt, _, jac = o.metrics()
+    # size of one mapped flux difference term: |U| (|u| + c) |mt| J
+    scale = (np.abs(U).max(axis=1) + 2e5) * 600.0 * np.abs(mt).max() * jac.max()
+    assert (np.abs(d).max(axis=1) / scale).max() < 1e-13
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS + [synth.VISC_OFF])
+@pytest.mark.parametrize("stretched", [False, True])
+def test_rectilinear_grid_as_curvilinear(flags, stretched):
+    """Uniform grids reproduce the rectilinear path to rounding; on the
+    stretched grid the curvilinear metrics are sixth-order differences of
+    the coordinates where the rectilinear path takes the exact map's
+    derivative, so only the uniform case is compared element by element."""
+    c = synth.small_case(n=(9, 7, 6), ns=4, nr=3, seed=5, laser=True, flags=flags, stretched=stretched)
+    c.laser.t0 = 0.0
+    o = Oracle(c)
+    U = o.prim_to_cons()
+    T = c.T.copy()
+    oc = Oracle(_curv_case(c, synth.as_curvilinear(c.grid)))
+    d0, h0 = o.rhs(U, T.copy(), want_hrr=True)
+    d1, h1 = oc.rhs(U, T.copy(), want_hrr=True)
+    err = (np.abs(d1 - d0).max(axis=1) / np.abs(d0).max(axis=1)).max()
+    if not stretched:
+        assert err < 1e-13
+        assert oc.stable_dt(U, T.copy()) == pytest.approx(o.stable_dt(U, T.copy()), rel=1e-14)
+        c0, c1 = o.cells(U, T.copy()), oc.cells(U, T.copy())
+        assert np.all(np.abs(c1 - c0).max(axis=1) <= 1e-13 * np.abs(c0).max(axis=1))
+        vol0 = np.array([o.cell_volume(q) for q in range(c.grid.N)])
+        vol1 = np.array([oc.cell_volume(q) for q in range(c.grid.N)])
+        assert np.allclose(vol1, vol0, rtol=1e-13, atol=0)
+    else:
+        assert err < 1e-2
+    assert np.array_equal(h0, h1)
+
+
+@pytest.mark.parametrize("visc", [True, False])
+def test_rotated_lattice_gives_the_rotated_rhs(visc):
+    """Central fluxes (linear in the stencil values): the right-hand side on
+    a rotated copy of the grid, with rotated velocities and laser centre,
+    is the Cartesian right-hand side with its momentum rows rotated."""
+    R = synth.rotation(0.4, -0.7, 1.1)
+    flags = synth.FORCE_CENTRAL | (0 if visc else synth.VISC_OFF)
+    c = synth.small_case(n=(9, 8, 7), ns=4, nr=3, seed=8, laser=True, flags=flags)
+    c.laser.t0 = 0.0
+    c.laser.sigma_r = 3e-4
+    o = Oracle(c)
+    U = o.prim_to_cons()
+    T = c.T.copy()
+    d0 = o.rhs(U, T.copy())
+    g = synth.affine_grid(c.grid.n, c.grid.spacing(), R)
+    las = synth.Laser(**{**c.laser.__dict__, "center": tuple(R @ np.array(c.laser.center))})
+    cr = synth.Case("rot", c.mech, g, c.Y, c.T, c.p, R @ c.vel, laser=las, flags=flags)
+    oc = Oracle(cr)
+    Ur = oc.prim_to_cons()
+    d1 = oc.rhs(Ur, T.copy())
+    ns = c.mech.ns
+    ref = d0.copy()
+    ref[ns:ns + 3] = R @ d0[ns:ns + 3]
+    err = np.abs(d1 - ref).max(axis=1) / np.abs(d0).max(axis=1)
+    assert err.max() < 1e-11, err
+    assert oc.stable_dt(Ur, T.copy()) == pytest.approx(o.stable_dt(U, T.copy()), rel=1e-12)
+    # per-cell fields, the sensor (invariant under rotation) and q_L included
+    c0, c1 = o.cells(U, T.copy()), oc.cells(Ur, T.copy())
+    assert np.all(np.abs(c1 - c0).max(axis=1) <= 1e-11 * np.abs(c0).max(axis=1))
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS)
+@pytest.mark.parametrize("kind", ["skewed", "wavy"])
+def test_flux_differences_conserve_on_a_skewed_grid(kind, flags):
+    """sum_q (1/J_q) dU/dt_q = sum of sources: the mapped flux differences
+    telescope over the periodic lattice."""
+    c = synth.small_case(n=(10, 9, 8), ns=4, nr=3, seed=6, laser=False, flags=flags | synth.CHEM_OFF)
+    g = _grid(kind, c.grid.n, c.grid.spacing())
+    o = Oracle(_curv_case(c, g))
+    U = o.prim_to_cons()
+    d = o.rhs(U, c.T.copy())
+    _, _, jac = o.metrics()
+    tot = (d / jac[None]).sum(axis=1)
+    scale = (np.abs(d) / jac[None]).sum(axis=1)
+    assert np.all(np.abs(tot) < 1e-13 * scale)
+
+
+@pytest.mark.parametrize("n,sigma", [((16, 14, 12), 2.5e-4), ((32, 30, 28), 1.5e-4)])
+def test_laser_integrates_to_the_energy_on_a_sheared_lattice(n, sigma):
+    """At t = t0 the spatial kernel integrates to E / (sqrt(2 pi) sigma_t)
+    over one period; on an affine lattice the nodal sum with the cell
+    volumes 1/J is that integral to spectral accuracy.  The centre sits
+    near a corner of the period cell; with the narrow kernel no further
+    images are summed (M = 0), so the nearest-image reduction carries the
+    wrap by itself."""
+    A = np.array([[1.0, 0.35, -0.2], [0.1, 1.0, 0.3], [0.25, -0.15, 1.0]])
+    g = synth.affine_grid(n, 1e-4, A)
+    mech = synth.make_mechanism(3, 1, 2)
+    N = g.N
+    las = synth.Laser(E=2e-4, center=tuple(A @ np.array([0.1e-3, n[1] * 1e-4 - 0.1e-3, 0.2e-3])), sigma_r=sigma,
+                      t0=1e-7, sigma_t=1e-7, on=True)
+    c = synth.Case("las", mech, g, np.full((3, N), 1 / 3), np.full(N, 500.0), np.full(N, 1e5), np.zeros((3, N)),
+                   laser=las, flags=synth.CHEM_OFF)
+    o = Oracle(c)
+    U = o.prim_to_cons()
+    cells = o.cells(U, c.T.copy(), t=las.t0)
+    qL = cells[5 + 2 * mech.ns + 1]
+    _, _, jac = o.metrics()
+    total = (qL / jac).sum()
+    assert total == pytest.approx(las.E / (np.sqrt(2 * np.pi) * las.sigma_t), rel=1e-10)
+
+
+@pytest.mark.slow
+def test_isentropic_vortex_on_the_skewed_grid():
+    """The paper's vortex-advection test on a skewed grid (Sec. 5.3.1 set-up,
+    beta = 0.2, t = 0.05): with sixth-order metrics the hybrid scheme keeps
+    high order, as on the Cartesian grid; measured order 3.9 from N = 32 to
+    64 (pre-asymptotic) and 7.1 from 64 to 128, error 6.5e-6 at 128."""
+    errs = []
+    for n in (32, 64, 128):
+        g = synth.skewed_grid((n, n, 1), 10.0 / n, beta=0.2)
+        c = synth.vortex_case_curv(g)
+        o = Oracle(c)
+        U = o.prim_to_cons()
+        T = c.T.copy()
+        ns, t = 25, 0.0
+        dt = 0.05 / ns
+        for _ in range(ns):
+            o.rk3_step(U, T, t, dt)
+            t += dt
+        x, y, _ = g.mesh()
+        rho = synth.vortex_exact(x[0] - 5.0, y[0] - 5.0, t)[0]
+        errs.append(np.max(np.abs(U[0] - rho.ravel())))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 5.0, (errs, orders)
+    assert errs[-1] < 2e-5
