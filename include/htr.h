@@ -132,6 +132,37 @@ typedef struct {
  * HTR_ENOMEM, HTR_EDEVICE. */
 htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, const htr_scheme* scheme,
                       htr_ctx** out);
+
+/* General curvilinear periodic grid (HOST pointers, copied), Sec. 5.2: the
+ * equations mapped to a uniform index space (spacing 1) with U~ = U/J and
+ * F~_d = (d xi_d / d x) . (F, G, H) / J, J = det(d xi / d x).
+ * xyz[3][N]: node coordinates x, y, z, node (i, j, k) at i + n0 (j + n1 k).
+ * period[a][c]: displacement of the node lattice when index a advances by
+ * n[a] (the image of node (i, j, k) n[a] cells further along a is at
+ * xyz + period[a]).  An inactive axis (n = 1) must have its period along its
+ * own coordinate, and the other periods no component along it. */
+typedef struct {
+  int32_t n[3];
+  const double* xyz;
+  double period[3][3];
+} htr_curv_grid_desc;
+
+/* Context on a curvilinear grid.  Metric terms are computed on the device
+ * in the conservative (Thomas-Lombard) form with sixth-order central
+ * differences, face values by the matching six-point interpolation, so a
+ * uniform flow is preserved to rounding.  Every single-grid entry point
+ * works on it (htr_rhs, htr_cells, htr_stable_dt, htr_rk3_step); the tape,
+ * the adjoint and the tiling/autotune calls return HTR_EUNSUPPORTED.
+ * Errors: HTR_EINVAL for an invalid lattice or a node where det(d x / d xi)
+ * is not positive. */
+htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid_desc* grid,
+                                  const htr_scheme* scheme, htr_ctx** out);
+
+/* Copies a curvilinear context's metric terms into caller DEVICE buffers:
+ * mt[10][N] ((d xi_d / d x_c) / J at row 3d + c, J at row 9) and mf[9][N]
+ * (the same at face i+1/2 along d).  Asynchronous on stream.  HTR_EINVAL on
+ * a rectilinear context. */
+htr_status htr_grid_metrics(htr_ctx* ctx, double* mt, double* mf, void* stream);
 /* Waits for the context's streams to drain and frees it.  NULL is HTR_EINVAL. */
 htr_status htr_destroy(htr_ctx* ctx);
 /* Replace the scheme flags of an existing context. */

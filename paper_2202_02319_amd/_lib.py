@@ -29,6 +29,10 @@ class htr_grid_desc(C.Structure):
                 ("L", C.c_double * 3)]
 
 
+class htr_curv_grid_desc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("xyz", _dp), ("period", (C.c_double * 3) * 3)]
+
+
 class htr_laser(C.Structure):
     _fields_ = [("E", C.c_double), ("center", C.c_double * 3), ("sigma_r", C.c_double), ("t0", C.c_double),
                 ("sigma_t", C.c_double), ("on", C.c_int32)]
@@ -65,6 +69,9 @@ def load():
     sig = {
         "htr_create": (st, [C.POINTER(htr_mech_desc), C.POINTER(htr_grid_desc), C.POINTER(htr_scheme),
                             C.POINTER(vp)]),
+        "htr_create_curvilinear": (st, [C.POINTER(htr_mech_desc), C.POINTER(htr_curv_grid_desc),
+                                        C.POINTER(htr_scheme), C.POINTER(vp)]),
+        "htr_grid_metrics": (st, [vp, vp, vp, vp]),
         "htr_destroy": (st, [vp]),
         "htr_set_flags": (st, [vp, C.c_uint32]),
         "htr_num_cells": (C.c_int64, [vp]),

@@ -241,11 +241,30 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   {
     TimedLaunch tl(C.timer, TC_POINT, s);
     HIP_OK(launch_point(C.ns, C.M, C.mem, C.nmem, C.nblocks, C.grid, a, U, T, w.aux, w.src, hrr,
-                        need_red ? w.blkred : nullptr, nullptr, w.status, want_dt, s));
+                        need_red ? w.blkred : nullptr, nullptr, w.status, want_dt, s, C.curv));
   }
   if (need_red) {
     TimedLaunch tl(C.timer, TC_REDUCE, s);
     HIP_OK(launch_finalize(C.mem, C.nmem, w.blkred, C.scheme.cfl, dt_out, J_dev, a.dt_dev, jcoef, want_dt, s));
+  }
+  if (C.curv) {
+    // curvilinear grid: mapped fluxes through per-face kernels, then the update
+    if (teno_bits) return fail(HTR_EUNSUPPORTED, "no tape on curvilinear grids");
+    {
+      TimedLaunch tl(C.timer, TC_SENSOR, s);
+      HIP_OK(launch_curv_igrad(C.ns, C.M, C.mem, C.nblocks, U, T, w.aux, C.cX, C.cdphi, s));
+      HIP_OK(launch_curv_sensor(C.mem, C.nblocks, *C.curv, w.aux, C.ns, w.flag, C.scheme.theta_c, nullptr, s));
+    }
+    {
+      TimedLaunch tl(C.timer, TC_CONV, s);
+      HIP_OK(launch_curv_faces(C.ns, C.M, C.mem, C.nblocks, *C.curv, a, U, T, w.aux, w.flag, C.cX, C.cdphi, C.cff,
+                               C.scheme.psi_c, C.scheme.teno_CT, s));
+    }
+    {
+      TimedLaunch tl(C.timer, TC_DIFF, s);
+      HIP_OK(launch_curv_update(C.ns, C.mem, C.nblocks, *C.curv, a, U, Un, w.src, C.cff, out, ca, cb, rhs_only, s));
+    }
+    return HTR_OK;
   }
   {
     TimedLaunch tl(C.timer, TC_SENSOR, s);
@@ -323,6 +342,13 @@ Ctx htr::view(const htr_ctx* c) {
     v.L1[a] = c->L[a];
   }
   v.timer = const_cast<Timer*>(&c->timer);
+  if (c->curv) {
+    const long long N = c->N;
+    v.curv = &c->cg;
+    v.cX = c->dcw;
+    v.cdphi = c->dcw + (long long)c->ns * N;
+    v.cff = v.cdphi + 3LL * (4 + c->ns) * N;
+  }
   return v;
 }
 
@@ -418,12 +444,123 @@ htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, cons
   return HTR_OK;
 }
 
+htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid_desc* grid,
+                                  const htr_scheme* scheme, htr_ctx** out) {
+  if (!out) return fail(HTR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !grid->xyz) return fail(HTR_EINVAL, "grid descriptor or its coordinates are NULL");
+  long long N = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (grid->n[a] < 1) return fail(HTR_EINVAL, "grid n[%d] = %d must be >= 1", a, grid->n[a]);
+    N *= grid->n[a];
+  }
+  for (long long q = 0; q < 3 * N; ++q)
+    if (!std::isfinite(grid->xyz[q])) return fail(HTR_EINVAL, "grid coordinates must be finite");
+  double P[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) {
+      P[a][c] = grid->period[a][c];
+      if (!std::isfinite(P[a][c])) return fail(HTR_EINVAL, "grid periods must be finite");
+    }
+  for (int a = 0; a < 3; ++a) {
+    if (grid->n[a] > 1) continue;
+    for (int c = 0; c < 3; ++c)
+      if (c != a && P[a][c] != 0.0)
+        return fail(HTR_EINVAL, "the period of inactive axis %d must lie along coordinate %d", a, a);
+    for (int b = 0; b < 3; ++b)
+      if (b != a && P[b][a] != 0.0)
+        return fail(HTR_EINVAL, "period %d must have no component along inactive axis %d", b, a);
+    if (!(P[a][a] != 0.0)) return fail(HTR_EINVAL, "the period of inactive axis %d is zero", a);
+  }
+  // B: columns P[a]; its inverse by cofactors
+  double B[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int a = 0; a < 3; ++a) B[r][a] = P[a][r];
+  const double det = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                     B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                     B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+  if (!(std::fabs(det) > 0)) return fail(HTR_EINVAL, "the lattice periods are linearly dependent");
+  CurvGeom g{};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+      g.Pinv[r][c] = (B[r1][c1] * B[r2][c2] - B[r1][c2] * B[r2][c1]) / det;
+      g.P[r][c] = P[r][c];
+    }
+  // distances between lattice planes (laser image counts), the period itself on an inactive axis
+  double h[3];
+  for (int a = 0; a < 3; ++a) {
+    const double* u = P[(a + 1) % 3];
+    const double* w = P[(a + 2) % 3];
+    const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    h[a] = grid->n[a] > 1 ? std::fabs(det) / std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2])
+                          : std::fabs(P[a][a]);
+  }
+  // the rectilinear arrays of the context are placeholders (unused on this grid)
+  std::vector<double> xn[3], one[3];
+  htr_grid_desc rd{};
+  for (int a = 0; a < 3; ++a) {
+    xn[a].assign(grid->n[a], 0.0);
+    one[a].assign(grid->n[a], 1.0);
+    rd.n[a] = grid->n[a];
+    rd.xnode[a] = xn[a].data();
+    rd.xi_node[a] = one[a].data();
+    rd.xi_face[a] = one[a].data();
+    rd.L[a] = h[a];
+  }
+  htr_ctx* c = nullptr;
+  htr_status st = htr_create(mech, &rd, scheme, &c);
+  if (st) return st;
+  auto bail = [&](htr_status s2) {
+    htr_destroy(c);
+    return s2;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&c->dcurv, sizeof(double) * 22 * N)) != hipSuccess)
+    return bail(fail(HTR_ENOMEM, "hipMalloc metrics: %s", hipGetErrorString(e)));
+  const long long nw = (long long)c->ns + 3LL * (4 + c->ns) + 3LL * (c->ns + 4);
+  if ((e = hipMalloc(&c->dcw, sizeof(double) * nw * N)) != hipSuccess)
+    return bail(fail(HTR_ENOMEM, "hipMalloc curvilinear scratch: %s", hipGetErrorString(e)));
+  double* mt = c->dcurv;
+  double* mf = c->dcurv + 10 * N;
+  double* xyz = c->dcurv + 19 * N;
+  if ((e = hipMemcpy(xyz, grid->xyz, sizeof(double) * 3 * N, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(fail(HTR_EDEVICE, "hipMemcpy coordinates: %s", hipGetErrorString(e)));
+  g.mt = mt;
+  g.mf = mf;
+  g.xyz = xyz;
+  if ((e = launch_curv_metrics(c->dmem, c->host_mem, g, mt, mf, nullptr)) != hipSuccess)
+    return bail(fail(HTR_EDEVICE, "metric kernels: %s", hipGetErrorString(e)));
+  std::vector<double> J(N);
+  if ((e = hipMemcpy(J.data(), mt + 9 * N, sizeof(double) * N, hipMemcpyDeviceToHost)) != hipSuccess)
+    return bail(fail(HTR_EDEVICE, "hipMemcpy J: %s", hipGetErrorString(e)));
+  for (long long q = 0; q < N; ++q)
+    if (!(J[q] > 0) || !std::isfinite(J[q]))
+      return bail(fail(HTR_EINVAL, "det(d x / d xi) is not positive at node %lld", q));
+  c->curv = true;
+  c->cg = g;
+  *out = c;
+  return HTR_OK;
+}
+
+htr_status htr_grid_metrics(htr_ctx* c, double* mt, double* mf, void* stream) {
+  if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (!c->curv) return fail(HTR_EINVAL, "not a curvilinear context");
+  if (!mt || !mf) return fail(HTR_EINVAL, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(mt, c->cg.mt, sizeof(double) * 10 * c->N, hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemcpyAsync(mf, c->cg.mf, sizeof(double) * 9 * c->N, hipMemcpyDeviceToDevice, s));
+  return HTR_OK;
+}
+
 htr_status htr_destroy(htr_ctx* c) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
   hipDeviceSynchronize();
   hipFree(c->dM);
   hipFree(c->dgrid);
   hipFree(c->dmem);
+  hipFree(c->dcurv);
+  hipFree(c->dcw);
   ws_free(c->ws);
   delete c;
   return HTR_OK;
@@ -477,8 +614,11 @@ htr_status htr_cells(htr_ctx* c, const double* U, double* T_io, double t, const 
   a.flags = c->scheme.flags;
   hipStream_t s = (hipStream_t)stream;
   HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T_io, c->ws.aux, c->ws.src, nullptr, nullptr, out,
-                      c->ws.status, 0, s));
-  HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, out, s));
+                      c->ws.status, 0, s, C.curv));
+  if (C.curv)
+    HIP_OK(launch_curv_sensor(C.mem, C.nblocks, *C.curv, c->ws.aux, C.ns, c->ws.flag, C.scheme.theta_c, out, s));
+  else
+    HIP_OK(launch_sensor(C.mem, 1, C.nblocks, 0, c->ws.aux, C.ns, c->ws.flag, c->ws.grad, C.scheme.theta_c, out, s));
   return HTR_OK;
 }
 
@@ -490,7 +630,7 @@ htr_status htr_stable_dt(htr_ctx* c, const double* U, double* T_io, double* dt_d
   a.flags = c->scheme.flags | HTR_CHEM_OFF;   // the step limit needs no chemistry
   hipStream_t s = (hipStream_t)stream;
   HIP_OK(launch_point(C.ns, C.M, C.mem, 1, C.nblocks, 0, a, U, T_io, c->ws.aux, c->ws.src, nullptr, c->ws.blkred,
-                      nullptr, c->ws.status, 1, s));
+                      nullptr, c->ws.status, 1, s, C.curv));
   HIP_OK(launch_finalize(C.mem, 1, c->ws.blkred, c->scheme.cfl, dt_dev, nullptr, nullptr, 0.0, 1, s));
   return HTR_OK;
 }
@@ -522,6 +662,7 @@ htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
   if (!U || !T_io || !t_dev || !dt_dev || !work || !tape) return fail(HTR_EINVAL, "NULL pointer");
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
+  if (c->curv) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for rectilinear grids");
   htr_status st = check_laser(laser);
   if (st) return st;
   Ctx C = view(c);

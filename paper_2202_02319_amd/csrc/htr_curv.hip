@@ -1,0 +1,541 @@
+// General curvilinear grids (Sec. 5.2, the mapped equations): metric terms,
+// sensor, mapped face fluxes and the stage update of a single-grid context.
+//
+// The equations are mapped to a uniform index space with U~ = U/J and
+// F~_d = (d xi_d / d x) . (F, G, H) / J along each index direction,
+// J = det(d xi / d x), index spacing 1.  Metric terms are evaluated in the
+// conservative form of Thomas & Lombard,
+//   (d xi_d / d x_c) / J = D_f[(D_e x_c1) x_c2] - D_e[(D_f x_c1) x_c2],
+// (d, e, f) and (c, c1, c2) cyclic, D the sixth-order central difference,
+// with the face values at i+1/2 the six-point interpolation whose face
+// difference is D: the sum over directions of face-metric differences is a
+// sum of commuting second differences, so a uniform flow stays uniform.
+//
+// Per stage: k_point (CURV variant: laser over lattice images, contravariant
+// dt limit, volume 1/J) -> mole fractions and index-space central
+// differences -> sensor -> one face kernel per direction (convective flux
+// of the hybrid scheme on the metric-projected flux, diffusive flux by the
+// chain rule) -> update.  These kernels are plain per-node/per-face
+// launches through L1/L2; the tiled LDS sweeps serve rectilinear grids.
+#include <hip/hip_runtime.h>
+
+#include "htr_dev.h"
+#include "htr_flux.h"
+
+namespace htr {
+
+__device__ __forceinline__ long long lin(const Member& G, int i, int j, int k) {
+  return ((long long)k * G.n[1] + j) * G.n[0] + i;
+}
+
+// Coordinate c of lattice node (i, j, k), any integers (a node n[a] cells
+// further along a is displaced by P[a]), minus x0.
+__device__ __forceinline__ double lat(const Member& G, const CurvGeom& g, int c, int i, int j, int k, double x0) {
+  const int id[3] = {i, j, k};
+  int w[3];
+  double sh = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w[a] = wrapi(id[a], G.n[a]);
+    sh += (double)((id[a] - w[a]) / G.n[a]) * g.P[a][c];
+  }
+  return (g.xyz[c * G.N + lin(G, w[0], w[1], w[2])] + sh) - x0;
+}
+
+__device__ __forceinline__ void step(int p[3], const int b[3], int e, int m) {
+  p[0] = b[0];
+  p[1] = b[1];
+  p[2] = b[2];
+  p[e] += m;
+}
+
+// D6 along e of coordinate c (relative to x0) at lattice point b.
+__device__ double d6x(const Member& G, const CurvGeom& g, int c, const int b[3], int e, double x0) {
+  const double w[3] = {45.0, -9.0, 1.0};
+  double s = 0.0;
+  for (int m = 1; m <= 3; ++m) {
+    int pp[3], pm[3];
+    step(pp, b, e, m);
+    step(pm, b, e, -m);
+    s += w[m - 1] * (lat(G, g, c, pp[0], pp[1], pp[2], x0) - lat(G, g, c, pm[0], pm[1], pm[2], x0));
+  }
+  return s / 60.0;
+}
+
+// D6 along o of the product (D6_e x_c1) x_c2 at lattice point b.
+__device__ double d6prod(const Member& G, const CurvGeom& g, int c1, int c2, const int b[3], int e, int o,
+                         const double x0[3]) {
+  const double w[3] = {45.0, -9.0, 1.0};
+  double s = 0.0;
+  for (int m = 1; m <= 3; ++m) {
+    int pp[3], pm[3];
+    step(pp, b, o, m);
+    step(pm, b, o, -m);
+    const double fp = d6x(G, g, c1, pp, e, x0[c1]) * lat(G, g, c2, pp[0], pp[1], pp[2], x0[c2]);
+    const double fm = d6x(G, g, c1, pm, e, x0[c1]) * lat(G, g, c2, pm[0], pm[1], pm[2], x0[c2]);
+    s += w[m - 1] * (fp - fm);
+  }
+  return s / 60.0;
+}
+
+// J = 1 / det(d x / d xi) at row 9, or 0 where the determinant is not
+// positive and finite (the host checks every node before accepting the grid).
+__global__ __launch_bounds__(BLK) void k_curv_metrics(const Member* __restrict__ mem, CurvGeom g,
+                                                      double* __restrict__ mt) {
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int b[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  double x0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x0[c] = g.xyz[c * N + q];
+  for (int d = 0; d < 3; ++d) {
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    for (int c = 0; c < 3; ++c) {
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      mt[(3 * d + c) * N + q] = d6prod(G, g, c1, c2, b, e, f, x0) - d6prod(G, g, c1, c2, b, f, e, x0);
+    }
+  }
+  double A[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int e = 0; e < 3; ++e) A[c][e] = d6x(G, g, c, b, e, x0[c]);
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  mt[9 * N + q] = (det > 0.0 && isfinite(det)) ? 1.0 / det : 0.0;
+}
+
+__global__ __launch_bounds__(BLK) void k_curv_face_metrics(const Member* __restrict__ mem,
+                                                           const double* __restrict__ mt, double* __restrict__ mf) {
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int b[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const double cw[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+  for (int d = 0; d < 3; ++d) {
+    long long st[6];
+    for (int m = 0; m < 6; ++m) {
+      int p[3] = {b[0], b[1], b[2]};
+      p[d] = wrapi(b[d] - 2 + m, G.n[d]);
+      st[m] = lin(G, p[0], p[1], p[2]);
+    }
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int m = 0; m < 6; ++m) s += cw[m] * mt[(3 * d + c) * N + st[m]];
+      mf[(3 * d + c) * N + q] = s / 60.0;
+    }
+  }
+}
+
+// theta = (div u)^2 / ((div u)^2 + |curl u|^2 + 1e-300), second-order central
+// differences through the chain rule d/dx_b = sum_a J mt[3a + b] d/d xi_a.
+__global__ __launch_bounds__(BLK) void k_curv_sensor(const Member* __restrict__ mem, CurvGeom g,
+                                                     const double* __restrict__ aux, int naux,
+                                                     unsigned char* __restrict__ flag, double theta_c,
+                                                     double* __restrict__ theta_out, int nq) {
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const double* vel = aux + 4 * N;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  const double Jq = g.mt[9 * N + q];
+  double gr[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) gr[b][m] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!G.act[a]) continue;
+    const long long qp = q + (wrapi(c[a] + 1, G.n[a]) - c[a]) * stride[a];
+    const long long qm = q + (wrapi(c[a] - 1, G.n[a]) - c[a]) * stride[a];
+    double du[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) du[m] = vel[m * N + qp] - vel[m * N + qm];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double mab = Jq * g.mt[(3 * a + b) * N + q];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) gr[b][m] += mab * du[m] / 2.0;
+    }
+  }
+  (void)naux;
+  const double div = gr[0][0] + gr[1][1] + gr[2][2];
+  const double wx = gr[1][2] - gr[2][1], wy = gr[2][0] - gr[0][2], wz = gr[0][1] - gr[1][0];
+  const double d2 = div * div;
+  const double th = d2 / (d2 + wx * wx + wy * wy + wz * wz + 1e-300);
+  flag[q] = th > theta_c ? 1 : 0;
+  if (theta_out) theta_out[(nq - 1) * N + q] = th;
+}
+
+// Mole fractions X_s = Y_s W / W_s.
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_curv_molefrac(const MechTables* __restrict__ M,
+                                                       const Member* __restrict__ mem, const double* __restrict__ U,
+                                                       double* __restrict__ X) {
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  double r[NS], rho = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    r[s] = U[s * N + q];
+    rho += r[s];
+  }
+  const double irho = 1.0 / rho;
+  double iW = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) iW += r[s] * irho * M->iW[s];
+  const double W = 1.0 / iW;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) X[s * N + q] = r[s] * irho * W * M->iW[s];
+}
+
+// Index-space central differences (phi(i+1) - phi(i-1)) / 2 of
+// phi = (u, v, w, T, X_s) along each axis (zero along an inactive axis).
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_curv_igrad(const Member* __restrict__ mem, const double* __restrict__ T,
+                                                    const double* __restrict__ aux, const double* __restrict__ X,
+                                                    double* __restrict__ dphi) {
+  constexpr int NP = 4 + NS;
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  for (int a = 0; a < 3; ++a) {
+    double* out = dphi + (long long)a * NP * N;
+    if (!G.act[a]) {
+      for (int k = 0; k < NP; ++k) out[k * N + q] = 0.0;
+      continue;
+    }
+    const long long qp = q + (wrapi(c[a] + 1, G.n[a]) - c[a]) * stride[a];
+    const long long qm = q + (wrapi(c[a] - 1, G.n[a]) - c[a]) * stride[a];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) out[m * N + q] = (aux[(4 + m) * N + qp] - aux[(4 + m) * N + qm]) / 2.0;
+    out[3 * N + q] = (T[qp] - T[qm]) / 2.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) out[(4 + s) * N + q] = (X[s * N + qp] - X[s * N + qm]) / 2.0;
+  }
+}
+
+// Mapped flux through face i+1/2 along d = blockIdx.y, stored at node i:
+// ff = (diffusive - convective) flux projected on the face metric vector n.
+// Convective: the hybrid switch of the rectilinear sweep (TENO where a
+// stencil node's sensor is set or the pressure jump across the face is
+// large), central six-point flux or TENO6 / WENO3-Z on the local
+// Lax-Friedrichs split with alpha = max |u . n| + c |n| over the stencil.
+// Diffusive: index-space derivatives at the face (normal from the two
+// nodes, tangential the mean of the two nodal central differences), the
+// chain rule with the face mean of d xi_e / d x, arithmetic-mean face
+// coefficients.
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                   CurvGeom g, unsigned flags, const double* __restrict__ U,
+                                                   const double* __restrict__ T, const double* __restrict__ aux,
+                                                   const unsigned char* __restrict__ flg,
+                                                   const double* __restrict__ X, const double* __restrict__ dphi,
+                                                   double* __restrict__ ff, double psi_c, double CT) {
+  constexpr int NV = NS + 4, NP = 4 + NS;
+  const Member& G = mem[0];
+  const int d = blockIdx.y;
+  if (!G.act[d]) return;
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int c0[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  long long st[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    int p[3] = {c0[0], c0[1], c0[2]};
+    p[d] = wrapi(c0[d] - 2 + m, G.n[d]);
+    st[m] = lin(G, p[0], p[1], p[2]);
+  }
+  const long long qa = st[2], qb = st[3];
+  const double n0 = g.mf[(3 * d) * N + q], n1 = g.mf[(3 * d + 1) * N + q], n2 = g.mf[(3 * d + 2) * N + q];
+  const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  double* out = ff + (long long)d * NV * N;
+
+  // ---- convective flux
+  double un[6], pm[6];
+  bool anyflag = false;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const long long k = st[m];
+    un[m] = aux[4 * N + k] * n0 + aux[5 * N + k] * n1 + aux[6 * N + k] * n2;
+    pm[m] = aux[k];
+    anyflag = anyflag || flg[k] != 0;
+  }
+  bool teno;
+  if (flags & HTR_FORCE_TENO) teno = true;
+  else if (flags & HTR_FORCE_CENTRAL) teno = false;
+  else {
+    const double pa = pm[2], pb = pm[3];
+    teno = anyflag || (fabs(pb - pa) / fmin(pa, pb) > psi_c);
+  }
+  double fc[NV];
+  if (!teno) {
+    const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const double Uv = U[v * N + st[m]];
+        double f;
+        if (v < NS) f = Uv * un[m];
+        else if (v < NS + 3) f = Uv * un[m] + pm[m] * (v == NS ? n0 : (v == NS + 1 ? n1 : n2));
+        else f = (Uv + pm[m]) * un[m];
+        s += cc[m] * f;
+      }
+      fc[v] = s / 60.0;
+    }
+  } else {
+    double alpha = -1.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) alpha = fmax(alpha, fabs(un[m]) + aux[N + st[m]] * nn);
+    const bool weno = (flags & HTR_WENO3Z) != 0;
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+      double fp[6], fmr[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const double Uv = U[v * N + st[m]];
+        double f;
+        if (v < NS) f = Uv * un[m];
+        else if (v < NS + 3) f = Uv * un[m] + pm[m] * (v == NS ? n0 : (v == NS + 1 ? n1 : n2));
+        else f = (Uv + pm[m]) * un[m];
+        fp[m] = 0.5 * (f + alpha * Uv);
+        fmr[5 - m] = 0.5 * (f - alpha * Uv);
+      }
+      fc[v] = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
+    }
+  }
+  if (flags & HTR_VISC_OFF) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * N + q] = -fc[v];
+    return;
+  }
+
+  // ---- diffusive flux
+  const double nv3[3] = {n0, n1, n2};
+  double Gf[3][3];   // d xi_e / d x_b at the face
+  const double Ja = g.mt[9 * N + qa], Jb = g.mt[9 * N + qb];
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      Gf[e][b] = 0.5 * (Ja * g.mt[(3 * e + b) * N + qa] + Jb * g.mt[(3 * e + b) * N + qb]);
+  const double* dpa = dphi + qa;
+  const double* dpb = dphi + qb;
+  // derivative along index axis e at the face of phi row k (values va, vb at the two nodes)
+  auto dxi = [&](int k, int e, double va, double vb) -> double {
+    if (e == d) return vb - va;
+    if (!G.act[e]) return 0.0;
+    return 0.5 * (dpa[((long long)e * NP + k) * N] + dpb[((long long)e * NP + k) * N]);
+  };
+  double gu[3][3];   // gu[b][m] = d u_m / d x_b
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double va = aux[(4 + m) * N + qa], vb = aux[(4 + m) * N + qb];
+    double de[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) de[e] = dxi(m, e, va, vb);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gu[b][m] = Gf[0][b] * de[0] + Gf[1][b] * de[1] + Gf[2][b] * de[2];
+  }
+  double rhoA = 0.0, rhoB = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    rhoA += U[s * N + qa];
+    rhoB += U[s * N + qb];
+  }
+  const double irA = 1.0 / rhoA, irB = 1.0 / rhoB;
+  double iWA = 0.0, iWB = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    iWA += U[s * N + qa] * irA * M->iW[s];
+    iWB += U[s * N + qb] * irB * M->iW[s];
+  }
+  const double TA = T[qa], TB = T[qb];
+  const double mu = 0.5 * (aux[2 * N + qa] + aux[2 * N + qb]);
+  const double lam = 0.5 * (aux[3 * N + qa] + aux[3 * N + qb]);
+  const double rho = 0.5 * (rhoA + rhoB);
+  const double W = 0.5 * (1.0 / iWA + 1.0 / iWB);
+  const double divu = gu[0][0] + gu[1][1] + gu[2][2];
+  double tn[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    tn[m] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double tau = mu * (gu[b][m] + gu[m][b]);
+      if (b == m) tau -= (2.0 / 3.0) * mu * divu;
+      tn[m] += nv3[b] * tau;
+    }
+  }
+  double Jn[NS], Yf[NS], hf[NS];
+  double corr = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double va = X[s * N + qa], vb = X[s * N + qb];
+    double de[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) de[e] = dxi(4 + s, e, va, vb);
+    double dXn = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dXn += (Gf[0][b] * de[0] + Gf[1][b] * de[1] + Gf[2][b] * de[2]) * nv3[b];
+    const double Df = 0.5 * (aux[(7 + s) * N + qa] + aux[(7 + s) * N + qb]);
+    Jn[s] = -rho * Df * (M->W[s] / W) * dXn;
+    corr += rho * Df * (M->W[s] / W) * dXn;
+    Yf[s] = 0.5 * (U[s * N + qa] * irA + U[s * N + qb] * irB);
+    hf[s] = 0.5 * (M->RW[s] * TA * hRTs(M, s, TA) + M->RW[s] * TB * hRTs(M, s, TB));
+  }
+  double gT[3];
+  {
+    double de[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) de[e] = dxi(3, e, TA, TB);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gT[b] = Gf[0][b] * de[0] + Gf[1][b] * de[1] + Gf[2][b] * de[2];
+  }
+  double qn = -lam * (gT[0] * n0 + gT[1] * n1 + gT[2] * n2);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    Jn[s] += Yf[s] * corr;
+    qn += Jn[s] * hf[s];
+  }
+  double work = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) work += tn[m] * 0.5 * (aux[(4 + m) * N + qa] + aux[(4 + m) * N + qb]);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) out[s * N + q] = -Jn[s] - fc[s];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) out[(NS + m) * N + q] = tn[m] - fc[NS + m];
+  out[(NS + 3) * N + q] = (work - qn) - fc[NS + 3];
+}
+
+// dU/dt = src + sum_d J (ff_d(i) - ff_d(i - e_d)); out = dU/dt (rhs_only) or
+// the stage combination ca U^n + cb (U + dt dU/dt).
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_curv_update(const Member* __restrict__ mem, CurvGeom g, CallArgs A,
+                                                     const double* __restrict__ U, const double* __restrict__ Un,
+                                                     const double* __restrict__ src, const double* __restrict__ ff,
+                                                     double* __restrict__ out, double ca, double cb, int rhs_only) {
+  constexpr int NV = NS + 4;
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  const double Jq = g.mt[9 * N + q];
+  double L[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) L[v] = v < NS ? src[v * N + q] : (v == NS + 3 ? src[NS * N + q] : 0.0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!G.act[d]) continue;
+    const long long qm = q + (wrapi(c[d] - 1, G.n[d]) - c[d]) * stride[d];
+    const double* f = ff + (long long)d * NV * N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) L[v] += Jq * (f[v * N + q] - f[v * N + qm]);
+  }
+  if (rhs_only) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * N + q] = L[v];
+    return;
+  }
+  const double dt = A.dt_dev[0];
+  double uv[NV], unv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    uv[v] = U[v * N + q];
+    unv[v] = ca != 0.0 ? Un[v * N + q] : 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double base = uv[v] + dt * L[v];
+    out[v * N + q] = ca != 0.0 ? ca * unv[v] + cb * base : cb * base;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int blocks_of(long long N) { return (int)((N + BLK - 1) / BLK); }
+
+hipError_t launch_curv_metrics(const Member* mem, const Member& host, const CurvGeom& g, double* mt, double* mf,
+                               hipStream_t s) {
+  const int nb = blocks_of(host.N);
+  hipLaunchKernelGGL(k_curv_metrics, dim3(nb), dim3(BLK), 0, s, mem, g, mt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_curv_face_metrics, dim3(nb), dim3(BLK), 0, s, mem, mt, mf);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_sensor(const Member* mem, int nblocks, const CurvGeom& g, const double* aux, int ns,
+                              unsigned char* flag, double theta_c, double* theta_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, g, aux, 7 + ns, flag, theta_c, theta_out,
+                     5 + 2 * ns + 3);
+  return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t igrad_t(const MechTables* M, const Member* mem, int nblocks, const double* U, const double* T,
+                          const double* aux, double* X, double* dphi, hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_molefrac<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, U, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_curv_igrad<NS>, dim3(nblocks), dim3(BLK), 0, s, mem, T, aux, X, dphi);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int nblocks, const double* U,
+                             const double* T, const double* aux, double* X, double* dphi, hipStream_t s) {
+#define C_(NS) igrad_t<NS>(M, mem, nblocks, U, T, aux, X, dphi, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+template <int NS>
+static hipError_t faces_t(const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g, unsigned flags,
+                          const double* U, const double* T, const double* aux, const unsigned char* flag,
+                          const double* X, const double* dphi, double* ff, double psi_c, double CT, hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_face<NS>, dim3(nblocks, 3), dim3(BLK), 0, s, M, mem, g, flags, U, T, aux, flag, X, dphi,
+                     ff, psi_c, CT);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_faces(int ns, const MechTables* M, const Member* mem, int nblocks,
+                             const CurvGeom& g, const CallArgs& a, const double* U, const double* T,
+                             const double* aux, const unsigned char* flag, const double* X, const double* dphi,
+                             double* ff, double psi_c, double teno_CT, hipStream_t s) {
+#define C_(NS) faces_t<NS>(M, mem, nblocks, g, a.flags, U, T, aux, flag, X, dphi, ff, psi_c, teno_CT, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+template <int NS>
+static hipError_t update_t(const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a, const double* U,
+                           const double* Un, const double* src, const double* ff, double* out, double ca, double cb,
+                           int rhs_only, hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_update<NS>, dim3(nblocks), dim3(BLK), 0, s, mem, g, a, U, Un, src, ff, out, ca, cb,
+                     rhs_only);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_update(int ns, const Member* mem, int nblocks, const CurvGeom& g,
+                              const CallArgs& a, const double* U, const double* Un, const double* src,
+                              const double* ff, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
+#define C_(NS) update_t<NS>(mem, nblocks, g, a, U, Un, src, ff, out, ca, cb, rhs_only, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+}  // namespace htr

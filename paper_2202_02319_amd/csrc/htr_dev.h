@@ -77,6 +77,16 @@ struct Member {
   const double* dlnA;         // nullable [nr]
 };
 
+// General curvilinear grid of a single-grid context (Sec. 5.2, the mapped
+// equations): metric terms at nodes and faces, node coordinates, lattice.
+struct CurvGeom {
+  const double* mt;    // [10][N]: (d xi_d / d x_c) / J at row 3d + c; J at row 9
+  const double* mf;    // [9][N]: the same at face i+1/2 along d
+  const double* xyz;   // [3][N] node coordinates
+  double P[3][3];      // P[a]: lattice displacement when index a advances by n[a]
+  double Pinv[3][3];   // inverse of the matrix whose columns are P[a]
+};
+
 // Per-call overrides used by the single-grid entry points.
 struct CallArgs {
   double t;                   // time of stage 0 (when t_dev is null)
@@ -160,10 +170,13 @@ struct Workspace;
 hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks,
                                const double* Y, const double* T, const double* p, const double* vel, double* U,
                                hipStream_t s);
+// cg (nullable): the curvilinear geometry of a single-grid context (laser
+// over lattice images, contravariant dt limit, volume 1/J)
 hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
                         const CallArgs& a,
                         const double* U, double* T, double* aux, double* src, double* hrr, double* blkred,
-                        double* cells_out, unsigned* status, int want_dt, hipStream_t s);
+                        double* cells_out, unsigned* status, int want_dt, hipStream_t s,
+                        const CurvGeom* cg = nullptr);
 hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, const double* aux, int ns,
                          unsigned char* flag,
                          double* grad, double theta_c, double* theta_out, hipStream_t s);
@@ -199,5 +212,29 @@ hipError_t launch_adjoint(int ns, const MechTables* M, const Member* mem, int nm
 hipError_t launch_adj_theta(const Member* mem, int nmem, const double* thpart, int nth, double* pbar,
                             hipStream_t st);
 hipError_t launch_axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);
+
+// Curvilinear grids (htr_curv.hip).  Metric terms of the node lattice
+// (xyz, P) into mt rows 0..8, J into row 9 (0 where det(d x / d xi) is not
+// positive and finite), face values into mf.
+hipError_t launch_curv_metrics(const Member* mem, const Member& host, const CurvGeom& g, double* mt, double* mf,
+                               hipStream_t s);
+// Sensor flags (and theta into theta_out row nq - 1 when non-null) by the chain rule.
+hipError_t launch_curv_sensor(const Member* mem, int nblocks, const CurvGeom& g, const double* aux, int ns,
+                              unsigned char* flag, double theta_c, double* theta_out, hipStream_t s);
+// Mole fractions X [ns][N] and index-space central differences of
+// (u, v, w, T, X_s) along each active axis, dphi [3][4 + ns][N].
+hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int nblocks, const double* U,
+                             const double* T, const double* aux, double* X, double* dphi, hipStream_t s);
+// Mapped face fluxes (diffusive minus convective) ff [3][ns + 4][N], face
+// i+1/2 along d stored at node i.
+hipError_t launch_curv_faces(int ns, const MechTables* M, const Member* mem, int nblocks,
+                             const CurvGeom& g, const CallArgs& a, const double* U, const double* T,
+                             const double* aux, const unsigned char* flag, const double* X, const double* dphi,
+                             double* ff, double psi_c, double teno_CT, hipStream_t s);
+// dU/dt = src + J sum_d (ff_d(i) - ff_d(i - e_d)), then the stage combination
+// as the rectilinear sweep (or dU/dt itself when rhs_only).
+hipError_t launch_curv_update(int ns, const Member* mem, int nblocks, const CurvGeom& g,
+                              const CallArgs& a, const double* U, const double* Un, const double* src,
+                              const double* ff, double* out, double ca, double cb, int rhs_only, hipStream_t s);
 
 }  // namespace htr

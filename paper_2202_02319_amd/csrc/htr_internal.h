@@ -71,6 +71,11 @@ struct Ctx {
   int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
   double L1[3] = {1, 1, 1};
   Timer* timer = nullptr;
+  // curvilinear single grid (null: rectilinear sweeps)
+  const CurvGeom* curv = nullptr;
+  double* cX = nullptr;           // [ns][N] mole fractions
+  double* cdphi = nullptr;        // [3][4 + ns][N] index-space central differences
+  double* cff = nullptr;          // [3][ns + 4][N] mapped face fluxes
 };
 
 LaserDev make_laser(const htr_laser* L, const int n[3], const double Lp[3]);
@@ -126,6 +131,12 @@ struct htr_ctx {
   int grid = 0;                    // persistent grid (0: off)
   htr::Workspace ws;
   htr::Timer timer;
+  // curvilinear grid (htr_create_curvilinear); L above then holds the
+  // distances between lattice planes (laser image counts)
+  bool curv = false;
+  htr::CurvGeom cg{};
+  double* dcurv = nullptr;         // mt [10][N], mf [9][N], xyz [3][N]
+  double* dcw = nullptr;           // X [ns][N], dphi [3][4 + ns][N], ff [3][ns + 4][N]
 };
 
 // An ensemble (the opaque htr_batch of the C interface).

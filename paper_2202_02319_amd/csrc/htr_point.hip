@@ -54,6 +54,40 @@ __device__ __forceinline__ double laser_axis(const LaserDev& L, const Member& G,
   return g;
 }
 
+// Laser kernel on a curvilinear grid: the Gaussian of the distance to the
+// centre summed over the lattice images (nearest image in lattice
+// coordinates, then M[a] periods each way along the active axes; an
+// inactive axis drops its coordinate).
+__device__ __forceinline__ double laser_curv(const LaserDev& L, const Member& G, const CurvGeom& cg, long long q) {
+  const long long N = G.N;
+  double r[3], sl[3], rm[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = cg.xyz[c * N + q] - L.xc[c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double v = cg.Pinv[a][0] * r[0] + cg.Pinv[a][1] * r[1] + cg.Pinv[a][2] * r[2];
+    sl[a] = G.act[a] ? v - rint(v) : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) rm[c] = sl[0] * cg.P[0][c] + sl[1] * cg.P[1][c] + sl[2] * cg.P[2][c];
+  const double h = -0.5 / (L.sr * L.sr);
+  // no images along an inactive axis (its coordinate is dropped)
+  const int M0 = G.act[0] ? L.M[0] : 0, M1 = G.act[1] ? L.M[1] : 0, M2 = G.act[2] ? L.M[2] : 0;
+  double g = 0.0;
+  for (int m0 = -M0; m0 <= M0; ++m0)
+    for (int m1 = -M1; m1 <= M1; ++m1)
+      for (int m2 = -M2; m2 <= M2; ++m2) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double z = rm[c] - (m0 * cg.P[0][c] + m1 * cg.P[1][c] + m2 * cg.P[2][c]);
+          r2 += z * z;
+        }
+        g += exp(h * r2);
+      }
+  return g;
+}
+
 // ----------------------------------------------------------- prim -> cons
 template <int NS>
 __global__ __launch_bounds__(BLK) void k_prim_to_cons(const MechTables* __restrict__ M, const Member* __restrict__ mem,
@@ -93,14 +127,16 @@ __global__ __launch_bounds__(BLK) void k_prim_to_cons(const MechTables* __restri
 // aux rows per cell: 0 p, 1 c, 2 mu, 3 lambda, 4..6 velocity, 7.. D_s.
 // src rows: 0..NS-1 wdot_s, NS q_L.  blkred per block: {sum dV hrr, min dt limit}.
 // One logical block bl of 256 cells.
-template <int NS>
+// CURV: curvilinear single grid (laser over lattice images, contravariant
+// dt limit, cell volume 1/J from the metric terms in cg).
+template <int NS, bool CURV>
 __device__ __forceinline__ void point_block(int bl, const MechTables* __restrict__ M,
                                             const Member* __restrict__ mem, int nmem, const CallArgs& A,
                                             const double* __restrict__ Ub, double* __restrict__ Tb,
                                             double* __restrict__ auxb, double* __restrict__ srcb,
                                             double* __restrict__ hrrb, double* __restrict__ blkred,
                                             double* __restrict__ cellsb, unsigned* __restrict__ status,
-                                            int want_dt) {
+                                            int want_dt, const CurvGeom& cg) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   __shared__ double conc[NS][BLK];
   __shared__ double wred[2][BLK / 64];
@@ -297,16 +333,39 @@ __device__ __forceinline__ void point_block(int bl, const MechTables* __restrict
     if (L.on) {
       const double tk = (A.t_dev ? A.t_dev[m] : A.t) + (A.dt_dev ? A.tcoef * A.dt_dev[m] : 0.0);
       const double tt = (tk - L.t0) / L.st;
-      qL = L.E * L.norm * laser_axis(L, G, 0, i) * laser_axis(L, G, 1, jj) * laser_axis(L, G, 2, k) *
-           exp(-0.5 * tt * tt);
+      const double gs = CURV ? laser_curv(L, G, cg, q)
+                             : laser_axis(L, G, 0, i) * laser_axis(L, G, 1, jj) * laser_axis(L, G, 2, k);
+      qL = L.E * L.norm * gs * exp(-0.5 * tt * tt);
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) src[s * N + q] = om[s];
     src[NS * N + q] = qL;
     if (hrrb) hrrb[G.off + q] = hrr;
-    const double xi0 = G.xin[0][i], xi1 = G.xin[1][jj], xi2 = G.xin[2][k];
-    hdv = hrr / (xi0 * xi1 * xi2);
-    if (want_dt) {
+    if (CURV) {
+      const double Jq = cg.mt[9 * N + q];
+      hdv = hrr / Jq;
+      if (want_dt) {
+        // contravariant speeds |u . grad xi_a| + c |grad xi_a|, grad xi_a = J mt_a
+        double sc = 0.0, sd = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (!G.act[a]) continue;
+          const double g0 = Jq * cg.mt[(3 * a) * N + q], g1 = Jq * cg.mt[(3 * a + 1) * N + q],
+                       g2 = Jq * cg.mt[(3 * a + 2) * N + q];
+          const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+          sc += fabs(u * g0 + v * g1 + w * g2) + c * sqrt(gg);
+          sd += gg;
+        }
+        double nu = fmax(mu * irho, lam / (rho * cp));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) nu = fmax(nu, Ds[s]);
+        if (sc > 0.0) lim = 1.0 / sc;
+        if (!(flags & HTR_VISC_OFF) && sd > 0.0) lim = fmin(lim, 1.0 / (2.0 * sd * nu));
+      }
+    }
+    const double xi0 = CURV ? 1.0 : G.xin[0][i], xi1 = CURV ? 1.0 : G.xin[1][jj], xi2 = CURV ? 1.0 : G.xin[2][k];
+    if (!CURV) hdv = hrr / (xi0 * xi1 * xi2);
+    if (!CURV && want_dt) {
       double sc = 0.0, sd = 0.0;
       const double uu[3] = {u, v, w}, xx[3] = {xi0, xi1, xi2};
 #pragma unroll
@@ -363,7 +422,7 @@ __device__ __forceinline__ void point_block(int bl, const MechTables* __restrict
 
 // Grid-stride over the nlog logical blocks: one pass when the grid has one
 // block per logical block, persistent blocks when it has fewer.
-template <int NS, bool PERSIST>
+template <int NS, bool PERSIST, bool CURV>
 __global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables* __restrict__ M,
                                                                 const Member* __restrict__ mem, int nmem, int nlog,
                                                                 CallArgs A, const double* __restrict__ Ub,
@@ -371,13 +430,15 @@ __global__ __launch_bounds__(BLK, NS <= 9 ? 3 : 2) void k_point(const MechTables
                                                                 double* __restrict__ srcb, double* __restrict__ hrrb,
                                                                 double* __restrict__ blkred,
                                                                 double* __restrict__ cellsb,
-                                                                unsigned* __restrict__ status, int want_dt) {
+                                                                unsigned* __restrict__ status, int want_dt,
+                                                                CurvGeom cg) {
   if (!PERSIST) {
-    point_block<NS>(blockIdx.x, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt);
+    point_block<NS, CURV>(blockIdx.x, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt,
+                          cg);
     return;
   }
   for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
-    point_block<NS>(bl, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt);
+    point_block<NS, CURV>(bl, M, mem, nmem, A, Ub, Tb, auxb, srcb, hrrb, blkred, cellsb, status, want_dt, cg);
     __syncthreads();   // the next logical block reuses the LDS
   }
 }
@@ -509,13 +570,18 @@ static hipError_t prim_to_cons_t(const MechTables* M, const Member* mem, int nme
 template <int NS>
 static hipError_t point_t(const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
                           const CallArgs& a, const double* U, double* T, double* aux, double* src, double* hrr,
-                          double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s) {
-  if (grid < nblocks)
-    hipLaunchKernelGGL((k_point<NS, true>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux, src,
-                       hrr, blkred, cells, status, want_dt);
+                          double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s,
+                          const CurvGeom* cg) {
+  const CurvGeom none{};
+  if (cg)   // curvilinear single grid: one block per logical block
+    hipLaunchKernelGGL((k_point<NS, false, true>), dim3(nblocks), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T,
+                       aux, src, hrr, blkred, cells, status, want_dt, *cg);
+  else if (grid < nblocks)
+    hipLaunchKernelGGL((k_point<NS, true, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux,
+                       src, hrr, blkred, cells, status, want_dt, none);
   else
-    hipLaunchKernelGGL((k_point<NS, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux, src,
-                       hrr, blkred, cells, status, want_dt);
+    hipLaunchKernelGGL((k_point<NS, false, false>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, nblocks, a, U, T, aux,
+                       src, hrr, blkred, cells, status, want_dt, none);
   return hipGetLastError();
 }
 
@@ -532,9 +598,10 @@ hipError_t launch_prim_to_cons(int ns, const MechTables* M, const Member* mem, i
 
 hipError_t launch_point(int ns, const MechTables* M, const Member* mem, int nmem, int nblocks, int grid,
                         const CallArgs& a, const double* U, double* T, double* aux, double* src, double* hrr,
-                        double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s) {
+                        double* blkred, double* cells, unsigned* status, int want_dt, hipStream_t s,
+                        const CurvGeom* cg) {
   grid = grid_of(nblocks, grid);
-#define C_(NS) point_t<NS>(M, mem, nmem, nblocks, grid, a, U, T, aux, src, hrr, blkred, cells, status, want_dt, s)
+#define C_(NS) point_t<NS>(M, mem, nmem, nblocks, grid, a, U, T, aux, src, hrr, blkred, cells, status, want_dt, s, cg)
   HTR_NS_SWITCH(ns, C_)
 #undef C_
 }

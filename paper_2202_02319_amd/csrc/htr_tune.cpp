@@ -140,6 +140,7 @@ htr_status htr_tile_shape_check(const int32_t n[3], const int32_t shape[3]) {
 
 htr_status htr_set_tiling(htr_ctx* c, const int32_t shape[3], int32_t grid) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (c->curv) return fail(HTR_EUNSUPPORTED, "tiles and persistent grids apply to rectilinear grids");
   if (grid < 0) return fail(HTR_EINVAL, "grid must be >= 0");
   if (shape) {
     htr_status st = check_shape(c->host_mem, shape);
@@ -168,6 +169,7 @@ htr_status htr_get_tiling(const htr_ctx* c, int32_t shape[3], int32_t* grid) {
 htr_status htr_autotune(htr_ctx* c, const double* U, double* T_io, double* work, void* stream, int32_t shape_out[3],
                         int32_t* grid_out) {
   if (!c || !U || !T_io || !work) return fail(HTR_EINVAL, "NULL pointer");
+  if (c->curv) return fail(HTR_EUNSUPPORTED, "tiles and persistent grids apply to rectilinear grids");
   hipStream_t s = (hipStream_t)stream;
   const int act[3] = {c->host_mem.act[0], c->host_mem.act[1], c->host_mem.act[2]};
   std::array<int, 3> best_t = {c->host_mem.tdim[0], c->host_mem.tdim[1], c->host_mem.tdim[2]};

@@ -79,16 +79,26 @@ class Context:
         md.lnA, md.beta, md.Ea = dp(mech.lnA), dp(mech.beta), dp(mech.Ea)
         md.nu_f, md.nu_r = ip(mech.nu_f), ip(mech.nu_r)
         md.Tmin, md.Tmax = float(mech.Tmin), float(mech.Tmax)
-        gd = htr_grid_desc()
-        for a in range(3):
-            gd.n[a] = int(grid.n[a])
-            gd.xnode[a] = dp(grid.xnode[a])
-            gd.xi_node[a] = dp(grid.xin[a])
-            gd.xi_face[a] = dp(grid.xif[a])
-            gd.L[a] = float(grid.L[a])
         sc = htr_scheme(cfl=cfl, theta_c=theta_c, psi_c=psi_c, teno_CT=teno_CT, flags=flags)
         h = C.c_void_p()
-        check(lib.htr_create(C.byref(md), C.byref(gd), C.byref(sc), C.byref(h)))
+        self.curvilinear = hasattr(grid, "xyz")
+        if self.curvilinear:   # node coordinates and lattice periods
+            gd = _lib.htr_curv_grid_desc()
+            for a in range(3):
+                gd.n[a] = int(grid.n[a])
+                for c in range(3):
+                    gd.period[a][c] = float(grid.period[a][c])
+            gd.xyz = dp(np.asarray(grid.xyz).reshape(-1))
+            check(lib.htr_create_curvilinear(C.byref(md), C.byref(gd), C.byref(sc), C.byref(h)))
+        else:
+            gd = htr_grid_desc()
+            for a in range(3):
+                gd.n[a] = int(grid.n[a])
+                gd.xnode[a] = dp(grid.xnode[a])
+                gd.xi_node[a] = dp(grid.xin[a])
+                gd.xi_face[a] = dp(grid.xif[a])
+                gd.L[a] = float(grid.L[a])
+            check(lib.htr_create(C.byref(md), C.byref(gd), C.byref(sc), C.byref(h)))
         self.h = h
         self.lib = lib
         self.ns, self.nr = md.ns, md.nr
@@ -256,6 +266,12 @@ def htr_batch_autotune(b, U, T_io, work, stream=None):
     check(b.lib.htr_batch_autotune(b.h, _ptr(U), _ptr(T_io), _ptr(work), _stream(stream)))
     shapes = [htr_batch_get_tiling(b, m)[0] for m in range(b.nmem)]
     return shapes, htr_batch_get_tiling(b, 0)[1]
+
+
+def htr_grid_metrics(ctx, mt, mf, stream=None):
+    """Curvilinear context: node metric terms and J into mt [10][N], face
+    metric terms into mf [9][N] (device tensors)."""
+    check(ctx.lib.htr_grid_metrics(ctx.h, _ptr(mt), _ptr(mf), _stream(stream)))
 
 
 def htr_check(ctx, stream=None):
