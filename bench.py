@@ -77,6 +77,30 @@ KERNEL_SOURCES = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_tgv128.md")
 
 
+def curv_conv_bytes_per_cell(ns):
+    """Curvilinear convective face kernel, per cell and direction, each array
+    read once (perfect stencil reuse): U (ns+4), p, c, u, v, w (5), the face
+    metric vector (3), the sensor flag (1 byte); write the face flux (ns+4)."""
+    return 8 * (2 * (ns + 4) + 5 + 3) + 1
+
+
+def curv_diff_bytes_per_cell(ns):
+    """Curvilinear diffusive face kernel, per cell and direction: U (ns),
+    T, mu, lambda, u, v, w, D_s (6+ns), mole fractions (ns), the two
+    tangential index-space differences of (u, v, w, T, X_s) (2 (4+ns)),
+    node metric terms and J (10), face metric vector (3); write the face
+    flux (ns+4)."""
+    return 8 * (ns + 1 + (5 + ns) + ns + 2 * (4 + ns) + 10 + 3 + (ns + 4))
+
+
+def curv_update_bytes_per_cell(ns):
+    """Curvilinear update: the three directions' convective and diffusive
+    face fluxes (6 (ns+4)), U, U^n (stages 2 and 3: 2/3 on average),
+    sources (ns+1) and J in; U^(k+1) out."""
+    nv = ns + 4
+    return 8 * (6 * nv + nv + (2.0 / 3.0) * nv + (ns + 1) + 1 + nv)
+
+
 def kernel_source_hash(kernel):
     """Short SHA-256 of the source files a kernel is compiled from."""
     h = hashlib.sha256()
@@ -220,6 +244,66 @@ def ensemble_measure(steps, warm=1, sizes=None):
                       for n in Ns}, "persistent_grid": grid}
 
 
+def curvilinear_measure(steps, warm=2, n=128, amp=0.25):
+    """The 128^3 Taylor-Green state (9 species, 20 reactions) on a 128^3 wavy
+    curvilinear grid (every metric term varying along every axis): `steps`
+    SSP-RK3 steps with the in-step CFL dt through the curvilinear kernels,
+    per-kernel HIP-event durations, and the face and update kernels priced
+    against HBM with their algorithmic bytes."""
+    import torch
+    import synth
+    from paper_2202_02319_amd import htr
+    c2 = synth.case_c2(n=n)
+    grid = synth.wavy_grid(c2.grid.n, c2.grid.spacing(), amp=amp, seed=11)
+    case = synth.Case("tgv-curv", c2.mech, grid, c2.Y, c2.T, c2.p, c2.vel, flags=c2.flags)
+    ctx = htr.Context.from_case(case)
+    N = ctx.N
+    U = htr.cons_from_case(ctx, case)
+    T = htr.to_dev(case.T)
+    z = lambda: torch.zeros(1, dtype=torch.float64, device="cuda")  # noqa: E731
+    t, dt = z(), z()
+    work = ctx.new_work()
+
+    def step():
+        htr.htr_rk3_step(ctx, U, T, t, dt, 1, None, None, work, None)
+    for _ in range(warm):
+        step()
+    torch.cuda.synchronize()
+    htr.htr_check(ctx)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    htr.htr_check(ctx)
+    ms = e0.elapsed_time(e1) / steps
+    htr.htr_timing(ctx, 1)
+    for _ in range(steps):
+        step()
+    kt = htr.htr_timing_read(ctx)
+    htr.htr_timing(ctx, 0)
+    htr.htr_check(ctx)
+    avg = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    ns = case.mech.ns
+    kern = {}
+    for k, name, bpc in (("conv", "k_curv_conv", 3 * curv_conv_bytes_per_cell(ns)),
+                         ("diff", "k_curv_diff", 3 * curv_diff_bytes_per_cell(ns)),
+                         ("update", "k_curv_update", curv_update_bytes_per_cell(ns))):
+        ach = bpc * N / (avg[k] / 1e3) / 1e9
+        kern[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell": round(bpc, 1),
+                      "avg_ms": round(avg[k], 4)}
+    return {"workload": f"{n}^3 multicomponent Taylor-Green state on a {n}^3 wavy curvilinear grid, 9 species, "
+                        f"20 reactions, SSP-RK3 with in-step CFL dt", "cells": N, "steps": steps,
+            "value": N * 3 / (ms / 1e3), "unit": "cell-stage updates/s", "ms_per_step": ms,
+            "kernel_ms": {"point": round(avg["point"], 4), "molefrac+igrad+sensor": round(avg["sensor"], 4),
+                          "conv_faces": round(avg["conv"], 4), "diff_faces": round(avg["diff"], 4),
+                          "update": round(avg["update"], 4), "reduce": round(avg["reduce"], 4)},
+            "kernels": kern}
+
+
 def adjoint_measure(nsteps=50, every=10, n=64):
     """The adjoint workload: the 64^3 mixing layer, `nsteps` RK3 steps with a
     frozen dt, checkpoints every `every` steps; gradient of the time-
@@ -268,6 +352,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
+    ap.add_argument("--curv-steps", type=int, default=5,
+                    help="RK3 steps of the curvilinear-grid measurement (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles (no autotuning)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
@@ -378,6 +464,9 @@ def main():
     if args.adj_steps > 0:
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_measure(args.adj_steps)
+    if args.curv_steps > 0:
+        torch.cuda.empty_cache()
+        out["curvilinear"] = curvilinear_measure(args.curv_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     if args.calib_copy:

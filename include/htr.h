@@ -222,11 +222,13 @@ htr_status htr_rk3_step(htr_ctx* ctx, double* U, double* T_io, double* t_dev, do
 /* Kernel timing for diagnostics: while enabled, every kernel the context
  * launches is bracketed by HIP events on its stream.  htr_timing_read
  * synchronises and returns, per kernel class (0 per-cell point kernel,
- * 1 sensor, 2 convective flux sweep, 3 diffusive flux sweep with the stage
- * update, 4 reductions and small kernels), the summed milliseconds and
- * launch counts since htr_timing(ctx, 1).  ms and launches are HOST arrays
- * of HTR_TIMING_CLASSES entries. */
-#define HTR_TIMING_CLASSES 5
+ * 1 sensor (on curvilinear grids with the mole fractions and index-space
+ * differences), 2 convective flux sweep (curvilinear: face kernel),
+ * 3 diffusive flux sweep with the stage update (curvilinear: face kernel),
+ * 4 reductions and small kernels, 5 the curvilinear stage update), the
+ * summed milliseconds and launch counts since htr_timing(ctx, 1).  ms and
+ * launches are HOST arrays of HTR_TIMING_CLASSES entries. */
+#define HTR_TIMING_CLASSES 6
 htr_status htr_timing(htr_ctx* ctx, int enable);
 htr_status htr_timing_read(htr_ctx* ctx, double* ms, int64_t* launches);
 

@@ -257,12 +257,17 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
     }
     {
       TimedLaunch tl(C.timer, TC_CONV, s);
-      HIP_OK(launch_curv_faces(C.ns, C.M, C.mem, C.nblocks, *C.curv, a, U, T, w.aux, w.flag, C.cX, C.cdphi, C.cff,
-                               C.scheme.psi_c, C.scheme.teno_CT, s));
+      HIP_OK(launch_curv_conv(C.ns, C.mem, C.nblocks, *C.curv, a, U, w.aux, w.flag, C.cffc, C.scheme.psi_c,
+                              C.scheme.teno_CT, s));
+    }
+    if (!(a.flags & HTR_VISC_OFF)) {
+      TimedLaunch tl(C.timer, TC_DIFF, s);
+      HIP_OK(launch_curv_diff(C.ns, C.M, C.mem, C.nblocks, *C.curv, U, T, w.aux, C.cX, C.cdphi, C.cffd, s));
     }
     {
-      TimedLaunch tl(C.timer, TC_DIFF, s);
-      HIP_OK(launch_curv_update(C.ns, C.mem, C.nblocks, *C.curv, a, U, Un, w.src, C.cff, out, ca, cb, rhs_only, s));
+      TimedLaunch tl(C.timer, TC_UPDATE, s);
+      HIP_OK(launch_curv_update(C.ns, C.mem, C.nblocks, *C.curv, a, U, Un, w.src, C.cffc, C.cffd, out, ca, cb,
+                                rhs_only, s));
     }
     return HTR_OK;
   }
@@ -347,7 +352,8 @@ Ctx htr::view(const htr_ctx* c) {
     v.curv = &c->cg;
     v.cX = c->dcw;
     v.cdphi = c->dcw + (long long)c->ns * N;
-    v.cff = v.cdphi + 3LL * (4 + c->ns) * N;
+    v.cffc = v.cdphi + 3LL * (4 + c->ns) * N;
+    v.cffd = v.cffc + 3LL * (c->ns + 4) * N;
   }
   return v;
 }
@@ -518,7 +524,7 @@ htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid
   hipError_t e;
   if ((e = hipMalloc(&c->dcurv, sizeof(double) * 22 * N)) != hipSuccess)
     return bail(fail(HTR_ENOMEM, "hipMalloc metrics: %s", hipGetErrorString(e)));
-  const long long nw = (long long)c->ns + 3LL * (4 + c->ns) + 3LL * (c->ns + 4);
+  const long long nw = (long long)c->ns + 3LL * (4 + c->ns) + 6LL * (c->ns + 4);
   if ((e = hipMalloc(&c->dcw, sizeof(double) * nw * N)) != hipSuccess)
     return bail(fail(HTR_ENOMEM, "hipMalloc curvilinear scratch: %s", hipGetErrorString(e)));
   double* mt = c->dcurv;

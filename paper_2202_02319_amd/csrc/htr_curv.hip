@@ -13,9 +13,9 @@
 //
 // Per stage: k_point (CURV variant: laser over lattice images, contravariant
 // dt limit, volume 1/J) -> mole fractions and index-space central
-// differences -> sensor -> one face kernel per direction (convective flux
-// of the hybrid scheme on the metric-projected flux, diffusive flux by the
-// chain rule) -> update.  These kernels are plain per-node/per-face
+// differences -> sensor -> convective and diffusive face kernels (all
+// directions in one launch each: the hybrid scheme on the metric-projected
+// flux; the diffusive flux by the chain rule) -> update.  These kernels are plain per-node/per-face
 // launches through L1/L2; the tiled LDS sweeps serve rectilinear grids.
 #include <hip/hip_runtime.h>
 
@@ -225,24 +225,18 @@ __global__ __launch_bounds__(BLK) void k_curv_igrad(const Member* __restrict__ m
   }
 }
 
-// Mapped flux through face i+1/2 along d = blockIdx.y, stored at node i:
-// ff = (diffusive - convective) flux projected on the face metric vector n.
-// Convective: the hybrid switch of the rectilinear sweep (TENO where a
-// stencil node's sensor is set or the pressure jump across the face is
-// large), central six-point flux or TENO6 / WENO3-Z on the local
-// Lax-Friedrichs split with alpha = max |u . n| + c |n| over the stencil.
-// Diffusive: index-space derivatives at the face (normal from the two
-// nodes, tangential the mean of the two nodal central differences), the
-// chain rule with the face mean of d xi_e / d x, arithmetic-mean face
-// coefficients.
+// Mapped convective flux through face i+1/2 along d = blockIdx.y, stored at
+// node i: the hybrid switch of the rectilinear sweep (TENO where a stencil
+// node's sensor is set or the pressure jump across the face is large),
+// central six-point flux or TENO6 / WENO3-Z on the local Lax-Friedrichs
+// split with alpha = max |u . n| + c |n| over the stencil, of the physical
+// flux projected on the face metric vector n (held fixed on the stencil).
 template <int NS>
-__global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict__ M, const Member* __restrict__ mem,
-                                                   CurvGeom g, unsigned flags, const double* __restrict__ U,
-                                                   const double* __restrict__ T, const double* __restrict__ aux,
-                                                   const unsigned char* __restrict__ flg,
-                                                   const double* __restrict__ X, const double* __restrict__ dphi,
-                                                   double* __restrict__ ff, double psi_c, double CT) {
-  constexpr int NV = NS + 4, NP = 4 + NS;
+__global__ __launch_bounds__(BLK) void k_curv_conv(const Member* __restrict__ mem, CurvGeom g, unsigned flags,
+                                                   const double* __restrict__ U, const double* __restrict__ aux,
+                                                   const unsigned char* __restrict__ flg, double* __restrict__ ffc,
+                                                   double psi_c, double CT) {
+  constexpr int NV = NS + 4;
   const Member& G = mem[0];
   const int d = blockIdx.y;
   if (!G.act[d]) return;
@@ -257,10 +251,9 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
     p[d] = wrapi(c0[d] - 2 + m, G.n[d]);
     st[m] = lin(G, p[0], p[1], p[2]);
   }
-  const long long qa = st[2], qb = st[3];
   const double n0 = g.mf[(3 * d) * N + q], n1 = g.mf[(3 * d + 1) * N + q], n2 = g.mf[(3 * d + 2) * N + q];
   const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  double* out = ff + (long long)d * NV * N;
+  double* out = ffc + (long long)d * NV * N;
 
   // ---- convective flux
   double un[6], pm[6];
@@ -279,7 +272,6 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
     const double pa = pm[2], pb = pm[3];
     teno = anyflag || (fabs(pb - pa) / fmin(pa, pb) > psi_c);
   }
-  double fc[NV];
   if (!teno) {
     const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
 #pragma unroll 1
@@ -294,7 +286,7 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
         else f = (Uv + pm[m]) * un[m];
         s += cc[m] * f;
       }
-      fc[v] = s / 60.0;
+      out[v * N + q] = s / 60.0;
     }
   } else {
     double alpha = -1.0;
@@ -314,15 +306,37 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
         fp[m] = 0.5 * (f + alpha * Uv);
         fmr[5 - m] = 0.5 * (f - alpha * Uv);
       }
-      fc[v] = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
+      out[v * N + q] = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
     }
   }
-  if (flags & HTR_VISC_OFF) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v * N + q] = -fc[v];
-    return;
-  }
+}
 
+// Mapped diffusive flux through face i+1/2 along d = blockIdx.y, stored at
+// node i: index-space derivatives at the face (normal from the two nodes,
+// tangential the mean of the two nodal central differences), physical
+// gradients by the chain rule with the face mean of d xi_e / d x, the flux
+// vector projected on the face metric vector n; arithmetic-mean face
+// coefficients.
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_curv_diff(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                                   CurvGeom g, const double* __restrict__ U,
+                                                   const double* __restrict__ T, const double* __restrict__ aux,
+                                                   const double* __restrict__ X, const double* __restrict__ dphi,
+                                                   double* __restrict__ ffd) {
+  constexpr int NS_ = NS, NV = NS + 4, NP = 4 + NS;
+  (void)NS_;
+  const Member& G = mem[0];
+  const int d = blockIdx.y;
+  if (!G.act[d]) return;
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int c0[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  int pb[3] = {c0[0], c0[1], c0[2]};
+  pb[d] = wrapi(c0[d] + 1, G.n[d]);
+  const long long qa = q, qb = lin(G, pb[0], pb[1], pb[2]);
+  const double n0 = g.mf[(3 * d) * N + q], n1 = g.mf[(3 * d + 1) * N + q], n2 = g.mf[(3 * d + 2) * N + q];
+  double* out = ffd + (long long)d * NV * N;
   // ---- diffusive flux
   const double nv3[3] = {n0, n1, n2};
   double Gf[3][3];   // d xi_e / d x_b at the face
@@ -380,10 +394,10 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
       tn[m] += nv3[b] * tau;
     }
   }
-  double Jn[NS], Yf[NS], hf[NS];
-  double corr = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
+  // species: two passes (the correction flux first, then each species),
+  // recomputing the face normal derivative rather than holding per-species
+  // arrays, which keeps the kernel's register footprint small
+  auto rhoDW_dXn = [&](int s) -> double {
     const double va = X[s * N + qa], vb = X[s * N + qb];
     double de[3];
 #pragma unroll
@@ -392,11 +406,11 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
 #pragma unroll
     for (int b = 0; b < 3; ++b) dXn += (Gf[0][b] * de[0] + Gf[1][b] * de[1] + Gf[2][b] * de[2]) * nv3[b];
     const double Df = 0.5 * (aux[(7 + s) * N + qa] + aux[(7 + s) * N + qb]);
-    Jn[s] = -rho * Df * (M->W[s] / W) * dXn;
-    corr += rho * Df * (M->W[s] / W) * dXn;
-    Yf[s] = 0.5 * (U[s * N + qa] * irA + U[s * N + qb] * irB);
-    hf[s] = 0.5 * (M->RW[s] * TA * hRTs(M, s, TA) + M->RW[s] * TB * hRTs(M, s, TB));
-  }
+    return rho * Df * (M->W[s] / W) * dXn;
+  };
+  double corr = 0.0;
+#pragma unroll 1
+  for (int s = 0; s < NS; ++s) corr += rhoDW_dXn(s);
   double gT[3];
   {
     double de[3];
@@ -406,28 +420,30 @@ __global__ __launch_bounds__(BLK) void k_curv_face(const MechTables* __restrict_
     for (int b = 0; b < 3; ++b) gT[b] = Gf[0][b] * de[0] + Gf[1][b] * de[1] + Gf[2][b] * de[2];
   }
   double qn = -lam * (gT[0] * n0 + gT[1] * n1 + gT[2] * n2);
-#pragma unroll
+#pragma unroll 1
   for (int s = 0; s < NS; ++s) {
-    Jn[s] += Yf[s] * corr;
-    qn += Jn[s] * hf[s];
+    const double Yf = 0.5 * (U[s * N + qa] * irA + U[s * N + qb] * irB);
+    const double hf = 0.5 * (M->RW[s] * TA * hRTs(M, s, TA) + M->RW[s] * TB * hRTs(M, s, TB));
+    const double Jn = -rhoDW_dXn(s) + Yf * corr;
+    qn += Jn * hf;
+    out[s * N + q] = -Jn;
   }
   double work = 0.0;
 #pragma unroll
   for (int m = 0; m < 3; ++m) work += tn[m] * 0.5 * (aux[(4 + m) * N + qa] + aux[(4 + m) * N + qb]);
 #pragma unroll
-  for (int s = 0; s < NS; ++s) out[s * N + q] = -Jn[s] - fc[s];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) out[(NS + m) * N + q] = tn[m] - fc[NS + m];
-  out[(NS + 3) * N + q] = (work - qn) - fc[NS + 3];
+  for (int m = 0; m < 3; ++m) out[(NS + m) * N + q] = tn[m];
+  out[(NS + 3) * N + q] = work - qn;
 }
 
-// dU/dt = src + sum_d J (ff_d(i) - ff_d(i - e_d)); out = dU/dt (rhs_only) or
-// the stage combination ca U^n + cb (U + dt dU/dt).
+// dU/dt = src + sum_d J ((Fd_d(i) - Fd_d(i - e_d)) - (Fc_d(i) - Fc_d(i - e_d)));
+// out = dU/dt (rhs_only) or the stage combination ca U^n + cb (U + dt dU/dt).
 template <int NS>
 __global__ __launch_bounds__(BLK) void k_curv_update(const Member* __restrict__ mem, CurvGeom g, CallArgs A,
                                                      const double* __restrict__ U, const double* __restrict__ Un,
-                                                     const double* __restrict__ src, const double* __restrict__ ff,
-                                                     double* __restrict__ out, double ca, double cb, int rhs_only) {
+                                                     const double* __restrict__ src, const double* __restrict__ ffc,
+                                                     const double* __restrict__ ffd, double* __restrict__ out,
+                                                     double ca, double cb, int rhs_only) {
   constexpr int NV = NS + 4;
   const Member& G = mem[0];
   const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
@@ -443,9 +459,16 @@ __global__ __launch_bounds__(BLK) void k_curv_update(const Member* __restrict__ 
   for (int d = 0; d < 3; ++d) {
     if (!G.act[d]) continue;
     const long long qm = q + (wrapi(c[d] - 1, G.n[d]) - c[d]) * stride[d];
-    const double* f = ff + (long long)d * NV * N;
+    const double* fc = ffc + (long long)d * NV * N;
+    const double* fd = ffd + (long long)d * NV * N;
+    if (A.flags & HTR_VISC_OFF) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) L[v] += Jq * (f[v * N + q] - f[v * N + qm]);
+      for (int v = 0; v < NV; ++v) L[v] += Jq * (0.0 - (fc[v * N + q] - fc[v * N + qm]));
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        L[v] += Jq * ((fd[v * N + q] - fd[v * N + qm]) - (fc[v * N + q] - fc[v * N + qm]));
+    }
   }
   if (rhs_only) {
 #pragma unroll
@@ -504,36 +527,51 @@ hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int
 }
 
 template <int NS>
-static hipError_t faces_t(const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g, unsigned flags,
-                          const double* U, const double* T, const double* aux, const unsigned char* flag,
-                          const double* X, const double* dphi, double* ff, double psi_c, double CT, hipStream_t s) {
-  hipLaunchKernelGGL(k_curv_face<NS>, dim3(nblocks, 3), dim3(BLK), 0, s, M, mem, g, flags, U, T, aux, flag, X, dphi,
-                     ff, psi_c, CT);
+static hipError_t conv_t(const Member* mem, int nblocks, const CurvGeom& g, unsigned flags, const double* U,
+                         const double* aux, const unsigned char* flag, double* ffc, double psi_c, double CT,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_conv<NS>, dim3(nblocks, 3), dim3(BLK), 0, s, mem, g, flags, U, aux, flag, ffc, psi_c, CT);
   return hipGetLastError();
 }
 
-hipError_t launch_curv_faces(int ns, const MechTables* M, const Member* mem, int nblocks,
-                             const CurvGeom& g, const CallArgs& a, const double* U, const double* T,
-                             const double* aux, const unsigned char* flag, const double* X, const double* dphi,
-                             double* ff, double psi_c, double teno_CT, hipStream_t s) {
-#define C_(NS) faces_t<NS>(M, mem, nblocks, g, a.flags, U, T, aux, flag, X, dphi, ff, psi_c, teno_CT, s)
+hipError_t launch_curv_conv(int ns, const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a,
+                            const double* U, const double* aux, const unsigned char* flag, double* ffc, double psi_c,
+                            double teno_CT, hipStream_t s) {
+#define C_(NS) conv_t<NS>(mem, nblocks, g, a.flags, U, aux, flag, ffc, psi_c, teno_CT, s)
+  HTR_NS_SWITCH(ns, C_)
+#undef C_
+}
+
+template <int NS>
+static hipError_t diff_t(const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g, const double* U,
+                         const double* T, const double* aux, const double* X, const double* dphi, double* ffd,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_diff<NS>, dim3(nblocks, 3), dim3(BLK), 0, s, M, mem, g, U, T, aux, X, dphi, ffd);
+  return hipGetLastError();
+}
+
+hipError_t launch_curv_diff(int ns, const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g,
+                            const double* U, const double* T, const double* aux, const double* X,
+                            const double* dphi, double* ffd, hipStream_t s) {
+#define C_(NS) diff_t<NS>(M, mem, nblocks, g, U, T, aux, X, dphi, ffd, s)
   HTR_NS_SWITCH(ns, C_)
 #undef C_
 }
 
 template <int NS>
 static hipError_t update_t(const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a, const double* U,
-                           const double* Un, const double* src, const double* ff, double* out, double ca, double cb,
-                           int rhs_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_curv_update<NS>, dim3(nblocks), dim3(BLK), 0, s, mem, g, a, U, Un, src, ff, out, ca, cb,
+                           const double* Un, const double* src, const double* ffc, const double* ffd, double* out,
+                           double ca, double cb, int rhs_only, hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_update<NS>, dim3(nblocks), dim3(BLK), 0, s, mem, g, a, U, Un, src, ffc, ffd, out, ca, cb,
                      rhs_only);
   return hipGetLastError();
 }
 
 hipError_t launch_curv_update(int ns, const Member* mem, int nblocks, const CurvGeom& g,
                               const CallArgs& a, const double* U, const double* Un, const double* src,
-                              const double* ff, double* out, double ca, double cb, int rhs_only, hipStream_t s) {
-#define C_(NS) update_t<NS>(mem, nblocks, g, a, U, Un, src, ff, out, ca, cb, rhs_only, s)
+                              const double* ffc, const double* ffd, double* out, double ca, double cb, int rhs_only,
+                              hipStream_t s) {
+#define C_(NS) update_t<NS>(mem, nblocks, g, a, U, Un, src, ffc, ffd, out, ca, cb, rhs_only, s)
   HTR_NS_SWITCH(ns, C_)
 #undef C_
 }

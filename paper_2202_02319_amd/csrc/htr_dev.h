@@ -225,16 +225,20 @@ hipError_t launch_curv_sensor(const Member* mem, int nblocks, const CurvGeom& g,
 // (u, v, w, T, X_s) along each active axis, dphi [3][4 + ns][N].
 hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int nblocks, const double* U,
                              const double* T, const double* aux, double* X, double* dphi, hipStream_t s);
-// Mapped face fluxes (diffusive minus convective) ff [3][ns + 4][N], face
-// i+1/2 along d stored at node i.
-hipError_t launch_curv_faces(int ns, const MechTables* M, const Member* mem, int nblocks,
-                             const CurvGeom& g, const CallArgs& a, const double* U, const double* T,
-                             const double* aux, const unsigned char* flag, const double* X, const double* dphi,
-                             double* ff, double psi_c, double teno_CT, hipStream_t s);
-// dU/dt = src + J sum_d (ff_d(i) - ff_d(i - e_d)), then the stage combination
-// as the rectilinear sweep (or dU/dt itself when rhs_only).
+// Mapped face fluxes [3][ns + 4][N], face i+1/2 along d stored at node i:
+// convective (the hybrid scheme on the metric-projected flux) and diffusive.
+hipError_t launch_curv_conv(int ns, const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a,
+                            const double* U, const double* aux, const unsigned char* flag, double* ffc, double psi_c,
+                            double teno_CT, hipStream_t s);
+hipError_t launch_curv_diff(int ns, const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g,
+                            const double* U, const double* T, const double* aux, const double* X,
+                            const double* dphi, double* ffd, hipStream_t s);
+// dU/dt = src + J sum_d ((ffd_d(i) - ffd_d(i - e_d)) - (ffc_d(i) - ffc_d(i - e_d)))
+// (ffd not read when HTR_VISC_OFF), then the stage combination as the
+// rectilinear sweep (or dU/dt itself when rhs_only).
 hipError_t launch_curv_update(int ns, const Member* mem, int nblocks, const CurvGeom& g,
                               const CallArgs& a, const double* U, const double* Un, const double* src,
-                              const double* ff, double* out, double ca, double cb, int rhs_only, hipStream_t s);
+                              const double* ffc, const double* ffd, double* out, double ca, double cb, int rhs_only,
+                              hipStream_t s);
 
 }  // namespace htr

@@ -34,7 +34,7 @@ struct Workspace {
 };
 
 // Timing classes (the order of htr_timing_read's arrays).
-enum { TC_POINT = 0, TC_SENSOR = 1, TC_CONV = 2, TC_DIFF = 3, TC_REDUCE = 4 };
+enum { TC_POINT = 0, TC_SENSOR = 1, TC_CONV = 2, TC_DIFF = 3, TC_REDUCE = 4, TC_UPDATE = 5 };
 
 // HIP-event kernel timer (diagnostics).
 struct Timer {
@@ -75,7 +75,8 @@ struct Ctx {
   const CurvGeom* curv = nullptr;
   double* cX = nullptr;           // [ns][N] mole fractions
   double* cdphi = nullptr;        // [3][4 + ns][N] index-space central differences
-  double* cff = nullptr;          // [3][ns + 4][N] mapped face fluxes
+  double* cffc = nullptr;         // [3][ns + 4][N] mapped convective face fluxes
+  double* cffd = nullptr;         // [3][ns + 4][N] mapped diffusive face fluxes
 };
 
 LaserDev make_laser(const htr_laser* L, const int n[3], const double Lp[3]);
@@ -136,7 +137,7 @@ struct htr_ctx {
   bool curv = false;
   htr::CurvGeom cg{};
   double* dcurv = nullptr;         // mt [10][N], mf [9][N], xyz [3][N]
-  double* dcw = nullptr;           // X [ns][N], dphi [3][4 + ns][N], ff [3][ns + 4][N]
+  double* dcw = nullptr;           // X [ns][N], dphi [3][4 + ns][N], ffc and ffd [3][ns + 4][N]
 };
 
 // An ensemble (the opaque htr_batch of the C interface).

@@ -170,7 +170,7 @@ def htr_timing(ctx, enable):
     check(ctx.lib.htr_timing(ctx.h, int(enable)))
 
 
-KERNEL_CLASSES = ("point", "sensor", "conv", "diff", "reduce")
+KERNEL_CLASSES = ("point", "sensor", "conv", "diff", "reduce", "update")
 
 
 def htr_timing_read(ctx):
