@@ -257,7 +257,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
     }
     {
       TimedLaunch tl(C.timer, TC_CONV, s);
-      HIP_OK(launch_curv_conv(C.ns, C.mem, C.nblocks, *C.curv, a, U, w.aux, w.flag, C.cffc, C.scheme.psi_c,
+      HIP_OK(launch_curv_conv(C.ns, *C.host1, C.mem, *C.curv, a, U, w.aux, w.flag, C.cffc, C.scheme.psi_c,
                               C.scheme.teno_CT, s));
     }
     if (!(a.flags & HTR_VISC_OFF)) {
@@ -350,6 +350,7 @@ Ctx htr::view(const htr_ctx* c) {
   if (c->curv) {
     const long long N = c->N;
     v.curv = &c->cg;
+    v.host1 = &c->host_mem;
     v.cX = c->dcw;
     v.cdphi = c->dcw + (long long)c->ns * N;
     v.cffc = v.cdphi + 3LL * (4 + c->ns) * N;

@@ -225,89 +225,140 @@ __global__ __launch_bounds__(BLK) void k_curv_igrad(const Member* __restrict__ m
   }
 }
 
-// Mapped convective flux through face i+1/2 along d = blockIdx.y, stored at
-// node i: the hybrid switch of the rectilinear sweep (TENO where a stencil
-// node's sensor is set or the pressure jump across the face is large),
-// central six-point flux or TENO6 / WENO3-Z on the local Lax-Friedrichs
-// split with alpha = max |u . n| + c |n| over the stencil, of the physical
-// flux projected on the face metric vector n (held fixed on the stencil).
-template <int NS>
-__global__ __launch_bounds__(BLK) void k_curv_conv(const Member* __restrict__ mem, CurvGeom g, unsigned flags,
+// Mapped convective flux through face i+1/2 along d, stored at node i: the
+// hybrid switch of the rectilinear sweep (TENO where a stencil node's sensor
+// is set or the pressure jump across the face is large), central six-point
+// flux or TENO6 / WENO3-Z on the local Lax-Friedrichs split with
+// alpha = max |u . n| + c |n| over the stencil, of the physical flux
+// projected on the face metric vector n (held fixed on the stencil).
+//
+// One block per tile of faces: CA faces along d by CB along the companion
+// axis o (x, or y when d is x), one plane r of the remaining axis.  The
+// tile's nodes and a 2 + 3 node halo along d are staged in LDS: first
+// velocity, p, c and the sensor flags (each face then keeps u . n, p, the
+// switch and alpha in registers), then the conserved variables one at a
+// time through a double buffer, one barrier per variable.  Every node value
+// is loaded once per block, coalesced along x.
+template <int CA, int CB>
+struct ConvTile {
+  static constexpr int NA = CA + 5;           // staged nodes along d
+  static constexpr int NB = NA * CB;          // staged nodes
+};
+
+template <int NS, int CA, int CB, bool DX>
+__global__ __launch_bounds__(BLK) void k_curv_conv(const Member* __restrict__ mem, CurvGeom g, int d, unsigned flags,
                                                    const double* __restrict__ U, const double* __restrict__ aux,
                                                    const unsigned char* __restrict__ flg, double* __restrict__ ffc,
                                                    double psi_c, double CT) {
-  constexpr int NV = NS + 4;
+  static_assert(CA * CB == BLK, "one face per thread");
+  constexpr int NV = NS + 4, NA = ConvTile<CA, CB>::NA, NB = ConvTile<CA, CB>::NB;
+  __shared__ double s_un[3][NB];   // velocity
+  __shared__ double s_p[NB], s_c[NB];
+  __shared__ unsigned char s_f[NB];
+  __shared__ double s_U[2][NB];
   const Member& G = mem[0];
-  const int d = blockIdx.y;
-  if (!G.act[d]) return;
-  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
-  if (q >= G.N) return;
   const long long N = G.N;
-  const int c0[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
-  long long st[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    int p[3] = {c0[0], c0[1], c0[2]};
-    p[d] = wrapi(c0[d] - 2 + m, G.n[d]);
-    st[m] = lin(G, p[0], p[1], p[2]);
+  // axes: d (faces), o (companion), r (plane)
+  const int o = DX ? 1 : 0;
+  const int r = 3 - d - o;
+  const int nto = (G.n[o] + CB - 1) / CB;
+  const int nta = (G.n[d] + CA - 1) / CA;
+  int b = blockIdx.x;
+  const int to = b % nto;
+  b /= nto;
+  const int ta = b % nta;
+  const int pr = b / nta;
+  const int a0 = ta * CA, o0 = to * CB;
+  const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+  // staged slot of node (k along d, j along o): x-consecutive threads read
+  // consecutive slots (DX: k is along x; otherwise j is)
+  auto slot = [](int k, int j) { return DX ? j * NA + k : k * CB + j; };
+  auto node = [&](int k, int j) -> long long {
+    const int ad = wrapi(a0 - 2 + k, G.n[d]);
+    const int ao = wrapi(o0 + j, G.n[o]);
+    return (long long)ad * stride[d] + (long long)ao * stride[o] + (long long)pr * stride[r];
+  };
+  for (int e = threadIdx.x; e < NB; e += BLK) {
+    const int k = DX ? e % NA : e / CB, j = DX ? e / NA : e % CB;
+    const long long q = node(k, j);
+    const int sl = slot(k, j);
+    s_un[0][sl] = aux[4 * N + q];
+    s_un[1][sl] = aux[5 * N + q];
+    s_un[2][sl] = aux[6 * N + q];
+    s_p[sl] = aux[q];
+    s_c[sl] = aux[N + q];
+    s_f[sl] = flg[q];
   }
-  const double n0 = g.mf[(3 * d) * N + q], n1 = g.mf[(3 * d + 1) * N + q], n2 = g.mf[(3 * d + 2) * N + q];
-  const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  double* out = ffc + (long long)d * NV * N;
-
-  // ---- convective flux
+  // this thread's face
+  const int fa = DX ? threadIdx.x % CA : threadIdx.x / CB;
+  const int fo = DX ? threadIdx.x / CA : threadIdx.x % CB;
+  const bool live = a0 + fa < G.n[d] && o0 + fo < G.n[o];
+  const long long qf = (long long)(a0 + fa) * stride[d] + (long long)(o0 + fo) * stride[o] + (long long)pr * stride[r];
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  if (live) {
+    n0 = g.mf[(3 * d) * N + qf];
+    n1 = g.mf[(3 * d + 1) * N + qf];
+    n2 = g.mf[(3 * d + 2) * N + qf];
+  }
+  __syncthreads();
   double un[6], pm[6];
   bool anyflag = false;
+  double alpha = -1.0;
+  const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    const long long k = st[m];
-    un[m] = aux[4 * N + k] * n0 + aux[5 * N + k] * n1 + aux[6 * N + k] * n2;
-    pm[m] = aux[k];
-    anyflag = anyflag || flg[k] != 0;
+    const int sl = slot(fa + m, fo);
+    un[m] = s_un[0][sl] * n0 + s_un[1][sl] * n1 + s_un[2][sl] * n2;
+    pm[m] = s_p[sl];
+    anyflag = anyflag || s_f[sl] != 0;
+    alpha = fmax(alpha, fabs(un[m]) + s_c[sl] * nn);
   }
   bool teno;
   if (flags & HTR_FORCE_TENO) teno = true;
   else if (flags & HTR_FORCE_CENTRAL) teno = false;
-  else {
-    const double pa = pm[2], pb = pm[3];
-    teno = anyflag || (fabs(pb - pa) / fmin(pa, pb) > psi_c);
-  }
-  if (!teno) {
-    const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+  else teno = anyflag || (fabs(pm[3] - pm[2]) / fmin(pm[2], pm[3]) > psi_c);
+  const bool weno = (flags & HTR_WENO3Z) != 0;
+  double* out = ffc + (long long)d * NV * N;
+  auto stage = [&](int v, int buf) {
+    for (int e = threadIdx.x; e < NB; e += BLK) {
+      const int k = DX ? e % NA : e / CB, j = DX ? e / NA : e % CB;
+      s_U[buf][slot(k, j)] = U[v * N + node(k, j)];
+    }
+  };
+  stage(0, 0);
+  __syncthreads();
 #pragma unroll 1
-    for (int v = 0; v < NV; ++v) {
-      double s = 0.0;
+  for (int v = 0; v < NV; ++v) {
+    const int buf = v & 1;
+    if (v + 1 < NV) stage(v + 1, buf ^ 1);
+    if (live) {
+      double f[6], Uv[6];
 #pragma unroll
       for (int m = 0; m < 6; ++m) {
-        const double Uv = U[v * N + st[m]];
-        double f;
-        if (v < NS) f = Uv * un[m];
-        else if (v < NS + 3) f = Uv * un[m] + pm[m] * (v == NS ? n0 : (v == NS + 1 ? n1 : n2));
-        else f = (Uv + pm[m]) * un[m];
-        s += cc[m] * f;
+        Uv[m] = s_U[buf][slot(fa + m, fo)];
+        if (v < NS) f[m] = Uv[m] * un[m];
+        else if (v < NS + 3) f[m] = Uv[m] * un[m] + pm[m] * (v == NS ? n0 : (v == NS + 1 ? n1 : n2));
+        else f[m] = (Uv[m] + pm[m]) * un[m];
       }
-      out[v * N + q] = s / 60.0;
-    }
-  } else {
-    double alpha = -1.0;
+      double res;
+      if (!teno) {
+        const double cc[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+        double sacc = 0.0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) alpha = fmax(alpha, fabs(un[m]) + aux[N + st[m]] * nn);
-    const bool weno = (flags & HTR_WENO3Z) != 0;
-#pragma unroll 1
-    for (int v = 0; v < NV; ++v) {
-      double fp[6], fmr[6];
+        for (int m = 0; m < 6; ++m) sacc += cc[m] * f[m];
+        res = sacc / 60.0;
+      } else {
+        double fp[6], fmr[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const double Uv = U[v * N + st[m]];
-        double f;
-        if (v < NS) f = Uv * un[m];
-        else if (v < NS + 3) f = Uv * un[m] + pm[m] * (v == NS ? n0 : (v == NS + 1 ? n1 : n2));
-        else f = (Uv + pm[m]) * un[m];
-        fp[m] = 0.5 * (f + alpha * Uv);
-        fmr[5 - m] = 0.5 * (f - alpha * Uv);
+        for (int m = 0; m < 6; ++m) {
+          fp[m] = 0.5 * (f[m] + alpha * Uv[m]);
+          fmr[5 - m] = 0.5 * (f[m] - alpha * Uv[m]);
+        }
+        res = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
       }
-      out[v * N + q] = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
+      out[v * N + qf] = res;
     }
+    __syncthreads();
   }
 }
 
@@ -526,18 +577,35 @@ hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int
 #undef C_
 }
 
+// Tiles of the convective face kernel: 64 x 4 faces in (x, y) when d is x,
+// 16 along d by 16 along x otherwise.
 template <int NS>
-static hipError_t conv_t(const Member* mem, int nblocks, const CurvGeom& g, unsigned flags, const double* U,
+static hipError_t conv_t(const Member& host, const Member* mem, const CurvGeom& g, unsigned flags, const double* U,
                          const double* aux, const unsigned char* flag, double* ffc, double psi_c, double CT,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_curv_conv<NS>, dim3(nblocks, 3), dim3(BLK), 0, s, mem, g, flags, U, aux, flag, ffc, psi_c, CT);
-  return hipGetLastError();
+  for (int d = 0; d < 3; ++d) {
+    if (!host.act[d]) continue;
+    if (d == 0) {
+      const int o = 1, r = 2;
+      const int nb = ((host.n[0] + 63) / 64) * ((host.n[o] + 3) / 4) * host.n[r];
+      hipLaunchKernelGGL((k_curv_conv<NS, 64, 4, true>), dim3(nb), dim3(BLK), 0, s, mem, g, d, flags, U, aux, flag,
+                         ffc, psi_c, CT);
+    } else {
+      const int o = 0, r = 3 - d;
+      const int nb = ((host.n[d] + 15) / 16) * ((host.n[o] + 15) / 16) * host.n[r];
+      hipLaunchKernelGGL((k_curv_conv<NS, 16, 16, false>), dim3(nb), dim3(BLK), 0, s, mem, g, d, flags, U, aux,
+                         flag, ffc, psi_c, CT);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t launch_curv_conv(int ns, const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a,
+hipError_t launch_curv_conv(int ns, const Member& host, const Member* mem, const CurvGeom& g, const CallArgs& a,
                             const double* U, const double* aux, const unsigned char* flag, double* ffc, double psi_c,
                             double teno_CT, hipStream_t s) {
-#define C_(NS) conv_t<NS>(mem, nblocks, g, a.flags, U, aux, flag, ffc, psi_c, teno_CT, s)
+#define C_(NS) conv_t<NS>(host, mem, g, a.flags, U, aux, flag, ffc, psi_c, teno_CT, s)
   HTR_NS_SWITCH(ns, C_)
 #undef C_
 }

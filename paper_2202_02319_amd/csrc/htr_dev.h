@@ -227,7 +227,7 @@ hipError_t launch_curv_igrad(int ns, const MechTables* M, const Member* mem, int
                              const double* T, const double* aux, double* X, double* dphi, hipStream_t s);
 // Mapped face fluxes [3][ns + 4][N], face i+1/2 along d stored at node i:
 // convective (the hybrid scheme on the metric-projected flux) and diffusive.
-hipError_t launch_curv_conv(int ns, const Member* mem, int nblocks, const CurvGeom& g, const CallArgs& a,
+hipError_t launch_curv_conv(int ns, const Member& host, const Member* mem, const CurvGeom& g, const CallArgs& a,
                             const double* U, const double* aux, const unsigned char* flag, double* ffc, double psi_c,
                             double teno_CT, hipStream_t s);
 hipError_t launch_curv_diff(int ns, const MechTables* M, const Member* mem, int nblocks, const CurvGeom& g,

@@ -73,6 +73,7 @@ struct Ctx {
   Timer* timer = nullptr;
   // curvilinear single grid (null: rectilinear sweeps)
   const CurvGeom* curv = nullptr;
+  const Member* host1 = nullptr;  // host copy of the single member (curvilinear launch shapes)
   double* cX = nullptr;           // [ns][N] mole fractions
   double* cdphi = nullptr;        // [3][4 + ns][N] index-space central differences
   double* cffc = nullptr;         // [3][ns + 4][N] mapped convective face fluxes
