@@ -137,3 +137,78 @@ def test_member_max_per_member(ens):
     ref2 = [max(ref[m], float(f2[b.offsets[m]:b.offsets[m + 1]].max())) for m in range(b.nmem)]
     assert host(out).tolist() == ref2
     htr.htr_batch_check(b)
+
+
+def test_full_size_ensemble():
+    """The ensemble workload at its full size (64 members, N^3 with N in
+    {32, ..., 96}, 22M cells), in the benchmark's launch configuration
+    (autotuned tiles per size class, graph replay):
+    - one batched RHS against the oracle on windows (5-cell halo) of three
+      members, one of them around its laser kernel, with each member's own
+      ln A offsets;
+    - three batched steps: the smallest member against the oracle's steps,
+      the largest against its own single-grid run, bit for bit."""
+    import dataclasses
+    from conftest import flux_floor, rhs_close
+    from gpu_util import sub_window
+    e = synth.ensemble_c4()
+    ctx = htr.Context(e.mech, e.members[0].grid)
+    b = htr.Batch.from_cases(ctx, e.members, e.dlnA)
+    U, T = htr.batch_state_from_cases(b, e.members)
+    work = b.new_work()
+    shapes, grid = htr.htr_batch_autotune(b, U, T.clone(), work)
+    t_eval = e.members[0].laser.t0
+    tt = torch.full((b.nmem,), t_eval, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(U)
+    htr.htr_rhs_batched(b, U, T.clone(), tt, out)
+    htr.htr_batch_check(b)
+    Uh, got = host(U), host(out)
+    sizes = [c.grid.n[0] for c in e.members]
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes)), 17]
+    rng = np.random.default_rng(4)
+    for k, m in enumerate(picks):
+        c = e.members[m]
+        mech_m = dataclasses.replace(e.mech, lnA=e.mech.lnA + e.dlnA[m])
+        cm = synth.Case(c.name, mech_m, c.grid, c.Y, c.T, c.p, c.vel, laser=c.laser)
+        n = c.grid.n
+        if k == 0:
+            lo = [int(np.argmin(np.abs(c.grid.xnode[a] - c.laser.center[a]))) - 4 for a in range(3)]
+        else:
+            lo = [int(rng.integers(0, n[a])) for a in range(3)]
+        sub, flat, inner = sub_window(cm, lo, (8, 8, 8), 5)
+        o = Oracle(sub)
+        Um = b.unpack(Uh, ctx.nv, m)[:, flat]
+        ref = o.rhs(Um, sub.T.copy(), t=t_eval)[:, inner]
+        p = o.cells(Um, sub.T.copy())[1]
+        ok, ratio = rhs_close(b.unpack(got, ctx.nv, m)[:, flat][:, inner], ref,
+                              flux_floor(Um, p, float(c.grid.xin[0][0]), o.ns), rel=1e-12)
+        assert ok, (m, ratio)
+    # three steps in the benchmark's configuration
+    z = lambda: torch.zeros(b.nmem, dtype=torch.float64, device="cuda")  # noqa: E731
+    t, dt, J = z(), z(), z()
+    U2, T2 = U.clone(), T.clone()
+    htr.htr_rk3_steps_batched(b, U2, T2, t, dt, 1, 3, work, J, use_graph=True)
+    htr.htr_batch_check(b)
+    U2h = host(U2)
+    ms, ml = picks[0], picks[1]
+    c = e.members[ms]
+    o = Oracle(c)
+    Uo, To, to, Jo = o.prim_to_cons(), c.T.copy(), 0.0, 0.0
+    for _ in range(3):
+        dto = o.stable_dt(Uo, To)
+        Jo = o.rk3_step(Uo, To, to, dto, lnA=e.mech.lnA + e.dlnA[ms], J=Jo)
+        to += dto
+    rho_c = float(Uo[:o.ns].sum(axis=0).max() * o.cells(Uo, To.copy())[2].max())
+    assert normwise_state(b.unpack(U2h, ctx.nv, ms), Uo, o.ns, rho_c).max() <= 1e-9
+    assert float(host(J)[ms]) == pytest.approx(Jo, rel=1e-9)
+    c = e.members[ml]
+    g = htr.Context(e.mech, c.grid)
+    htr.htr_set_tiling(g, shapes[ml], 0)
+    Ug, Tg = htr.cons_from_case(g, c), dev(c.T)
+    z1 = lambda: torch.zeros(1, dtype=torch.float64, device="cuda")  # noqa: E731
+    tg, dtg, Jg, wg = z1(), z1(), z1(), g.new_work()
+    for _ in range(3):
+        htr.htr_rk3_step(g, Ug, Tg, tg, dtg, 1, c.laser, dev(e.dlnA[ml]), wg, Jg)
+    htr.htr_check(g)
+    assert np.array_equal(host(Ug), b.unpack(U2h, ctx.nv, ml))
+    assert float(host(Jg)[0]) == float(host(J)[ml])
