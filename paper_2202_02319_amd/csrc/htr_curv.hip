@@ -132,7 +132,7 @@ __global__ __launch_bounds__(BLK) void k_curv_face_metrics(const Member* __restr
 // theta = (div u)^2 / ((div u)^2 + |curl u|^2 + 1e-300), second-order central
 // differences through the chain rule d/dx_b = sum_a J mt[3a + b] d/d xi_a.
 __global__ __launch_bounds__(BLK) void k_curv_sensor(const Member* __restrict__ mem, CurvGeom g,
-                                                     const double* __restrict__ aux, int naux,
+                                                     const double* __restrict__ aux,
                                                      unsigned char* __restrict__ flag, double theta_c,
                                                      double* __restrict__ theta_out, int nq) {
   const Member& G = mem[0];
@@ -163,7 +163,6 @@ __global__ __launch_bounds__(BLK) void k_curv_sensor(const Member* __restrict__ 
       for (int m = 0; m < 3; ++m) gr[b][m] += mab * du[m] / 2.0;
     }
   }
-  (void)naux;
   const double div = gr[0][0] + gr[1][1] + gr[2][2];
   const double wx = gr[1][2] - gr[2][1], wy = gr[2][0] - gr[0][2], wz = gr[0][1] - gr[1][0];
   const double d2 = div * div;
@@ -239,19 +238,15 @@ __global__ __launch_bounds__(BLK) void k_curv_igrad(const Member* __restrict__ m
 // switch and alpha in registers), then the conserved variables one at a
 // time through a double buffer, one barrier per variable.  Every node value
 // is loaded once per block, coalesced along x.
-template <int CA, int CB>
-struct ConvTile {
-  static constexpr int NA = CA + 5;           // staged nodes along d
-  static constexpr int NB = NA * CB;          // staged nodes
-};
-
 template <int NS, int CA, int CB, bool DX>
 __global__ __launch_bounds__(BLK) void k_curv_conv(const Member* __restrict__ mem, CurvGeom g, int d, unsigned flags,
                                                    const double* __restrict__ U, const double* __restrict__ aux,
                                                    const unsigned char* __restrict__ flg, double* __restrict__ ffc,
                                                    double psi_c, double CT) {
   static_assert(CA * CB == BLK, "one face per thread");
-  constexpr int NV = NS + 4, NA = ConvTile<CA, CB>::NA, NB = ConvTile<CA, CB>::NB;
+  constexpr int NV = NS + 4;
+  constexpr int NA = CA + 5;   // staged nodes along d
+  constexpr int NB = NA * CB;  // staged nodes
   __shared__ double s_un[3][NB];   // velocity
   __shared__ double s_p[NB], s_c[NB];
   __shared__ unsigned char s_f[NB];
@@ -374,8 +369,7 @@ __global__ __launch_bounds__(BLK) void k_curv_diff(const MechTables* __restrict_
                                                    const double* __restrict__ T, const double* __restrict__ aux,
                                                    const double* __restrict__ X, const double* __restrict__ dphi,
                                                    double* __restrict__ ffd) {
-  constexpr int NS_ = NS, NV = NS + 4, NP = 4 + NS;
-  (void)NS_;
+  constexpr int NV = NS + 4, NP = 4 + NS;
   const Member& G = mem[0];
   const int d = blockIdx.y;
   if (!G.act[d]) return;
@@ -555,7 +549,7 @@ hipError_t launch_curv_metrics(const Member* mem, const Member& host, const Curv
 
 hipError_t launch_curv_sensor(const Member* mem, int nblocks, const CurvGeom& g, const double* aux, int ns,
                               unsigned char* flag, double theta_c, double* theta_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_curv_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, g, aux, 7 + ns, flag, theta_c, theta_out,
+  hipLaunchKernelGGL(k_curv_sensor, dim3(nblocks), dim3(BLK), 0, s, mem, g, aux, flag, theta_c, theta_out,
                      5 + 2 * ns + 3);
   return hipGetLastError();
 }

@@ -411,7 +411,7 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
                                           const double* __restrict__ grad, double* Fd) {
   constexpr int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const bool a1 = G.act[t1], a2 = G.act[t2];
-  double uA[3], uB[3], g1A[3], g1B[3], g2A[3], g2B[3], rsA[NS], rsB[NS], DA[NS], DB[NS];
+  double uA[3], uB[3], g1A[3], g1B[3], g2A[3], g2B[3];
 #pragma unroll
   for (int mm = 0; mm < 3; ++mm) {
     uA[mm] = aux[(4 + mm) * N + qA];
@@ -424,13 +424,6 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
   const double muA = aux[2 * N + qA], muB = aux[2 * N + qB];
   const double laA = aux[3 * N + qA], laB = aux[3 * N + qB];
   const double TA = T[qA], TB = T[qB];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    rsA[s] = U[s * N + qA];
-    rsB[s] = U[s * N + qB];
-    DA[s] = aux[(7 + s) * N + qA];
-    DB[s] = aux[(7 + s) * N + qB];
-  }
   const double xf = G.xif[d][cAd];
   // velocity gradient at the face, g[a][mm] = d u_mm / d x_a
   double g[3][3];
@@ -453,37 +446,39 @@ __device__ __forceinline__ void diff_face(const MechTables* __restrict__ M, cons
   double rA = 0.0, rB = 0.0, nA = 0.0, nB = 0.0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    rA += rsA[s];
-    rB += rsB[s];
-    nA += rsA[s] * M->iW[s];
-    nB += rsB[s] * M->iW[s];
+    const double ra = U[s * N + qA], rb = U[s * N + qB];
+    rA += ra;
+    rB += rb;
+    nA += ra * M->iW[s];
+    nB += rb * M->iW[s];
   }
   const double rhof = 0.5 * (rA + rB);
   const double inA = 1.0 / nA, inB = 1.0 / nB, irA = 1.0 / rA, irB = 1.0 / rB;
   const double iWf = 1.0 / (0.5 * (rA * inA + rB * inB));
-  double term[NS];
-  double corr = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const double Df = 0.5 * (DA[s] + DB[s]);
+  // two passes over the species (the correction flux, then each flux),
+  // reloading per-species inputs rather than holding them in registers
+  auto term = [&](int s) -> double {
+    const double Df = 0.5 * (aux[(7 + s) * N + qA] + aux[(7 + s) * N + qB]);
     // both mole fractions rounded before differencing (no FMA across the
     // difference), so a uniform composition gives exactly zero flux
     double XA, XB;
     {
 #pragma clang fp contract(off)
-      XA = rsA[s] * M->iW[s] * inA;
-      XB = rsB[s] * M->iW[s] * inB;
+      XA = U[s * N + qA] * M->iW[s] * inA;
+      XB = U[s * N + qB] * M->iW[s] * inB;
     }
     const double dX = xf * (XB - XA);
-    term[s] = rhof * Df * (M->W[s] * iWf) * dX;
-    corr += term[s];
-  }
+    return rhof * Df * (M->W[s] * iWf) * dX;
+  };
+  double corr = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) corr += term(s);
   const double iTA = 1.0 / TA, iTB = 1.0 / TB;
   double qn = -lamf * xf * (TB - TA);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const double Yf = 0.5 * (rsA[s] * irA + rsB[s] * irB);
-    const double J = -term[s] + Yf * corr;
+    const double Yf = 0.5 * (U[s * N + qA] * irA + U[s * N + qB] * irB);
+    const double J = -term(s) + Yf * corr;
     const double hf = 0.5 * (M->RW[s] * TA * hRTi(M, s, TA, iTA) + M->RW[s] * TB * hRTi(M, s, TB, iTB));
     qn += J * hf;
     Fd[s] = -J;
