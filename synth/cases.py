@@ -436,6 +436,30 @@ def vortex_case_curv(grid: CurvGrid, L=10.0) -> Case:
     return _vortex_fields(mech, grid, x[0] - L / 2, y[0] - L / 2)
 
 
+def tgv2d_case(grid, L=2 * np.pi, u0=1.0, rho0=1.0, gamma=1.4, sigma=1.5e-11) -> Case:
+    """Two-dimensional Taylor-Green vortex of the paper's viscous accuracy
+    test (Sec. 5.3.1) in non-dimensional units: one species with R_u/W = 1
+    and gamma = 1.4, u = u0 sin(kx) cos(ky), v = -u0 cos(kx) sin(ky),
+    p = p0 + rho0 u0^2/4 (cos 2kx + cos 2ky) (k = 2 pi / L), rho = rho0,
+    Mach number u0 / c0 = 1e-2 / sqrt(gamma).  Fields at the physical node
+    coordinates of a rectilinear or curvilinear grid.  The Lennard-Jones
+    well depth is the reference temperature (T* = 1 there); the diameter
+    sets the viscosity, which the caller may rescale (mu scales as
+    1/sigma^2)."""
+    c0 = u0 * np.sqrt(gamma) / 1e-2
+    p0 = rho0 * c0 ** 2 / gamma
+    T0 = p0 / rho0
+    mech = single_species(RU, gamma / (gamma - 1), Tmin=0.5 * T0, Tmax=2.0 * T0, sigma=sigma, epsk=T0)
+    x, y, _ = grid.mesh()
+    x, y = x.ravel(), y.ravel()
+    k = 2 * np.pi / L
+    N = grid.N
+    p = p0 + rho0 * u0 ** 2 / 4 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    vel = np.stack([u0 * np.sin(k * x) * np.cos(k * y), -u0 * np.cos(k * x) * np.sin(k * y), np.zeros(N)])
+    return Case("tgv2d", mech, grid, np.ones((1, N)), p / rho0, p, vel, flags=CHEM_OFF,
+                meta={"u0": u0, "rho0": rho0, "k": k, "T0": T0})
+
+
 def vortex_exact(x, y, t=0.0, beta=5.0, alpha=0.5, r0=0.5, gamma=1.4, u0=1.0, v0=1.0, T0=1.0, L=10.0):
     """Exact advected vortex: primitive fields at time t (periodic images
     within one period are folded in by the minimum-image shift)."""

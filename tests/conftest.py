@@ -68,3 +68,12 @@ def rhs_close(a, b, floor, rel=1e-12):
     lim = np.maximum(rel * np.abs(b).max(axis=1), floor)
     r = np.abs(a - b).max(axis=1) / np.where(lim > 0, lim, 1)
     return bool(np.all(r <= 1.0)), r
+
+
+def golden(name):
+    """Rows of a cited text fixture under tests/golden/ (comment lines
+    starting with '#' skipped), each split on commas."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as fh:
+        return [ln.strip().split(",") for ln in fh if ln.strip() and not ln.startswith("#")]

@@ -8,6 +8,7 @@ import pytest
 
 import synth
 from oracle import Oracle
+from conftest import golden
 from oracle.oracle import omega11, omega22
 
 RU = 8.31446261815324
@@ -73,11 +74,13 @@ def test_newton_round_trip_and_guess_independence():
 # --------------------------------------------------------------- transport
 def test_collision_integral_fits_against_table():
     """Neufeld-Janzen-Aziz fits against the Hirschfelder-Curtiss-Bird table
-    (Lennard-Jones 12-6): Omega(2,2)* and Omega(1,1)* at T* = 1, 2."""
-    assert omega22(1.0) == pytest.approx(1.593, rel=2e-3)
-    assert omega11(1.0) == pytest.approx(1.440, rel=2e-3)
-    assert omega22(2.0) == pytest.approx(1.175, rel=2e-3)
-    assert omega11(2.0) == pytest.approx(1.075, rel=2e-3)
+    (Lennard-Jones 12-6; tests/golden/collision_integrals.csv): Omega(2,2)*
+    and Omega(1,1)* within the fits' 0.2%."""
+    rows = golden("collision_integrals.csv")
+    assert len(rows) >= 4
+    for Ts, o22, o11 in rows:
+        assert omega22(float(Ts)) == pytest.approx(float(o22), rel=2e-3), Ts
+        assert omega11(float(Ts)) == pytest.approx(float(o11), rel=2e-3), Ts
 
 
 def _two_species(W1, W2, s1, s2, e1, e2, cp1=3.5, cp2=3.5):

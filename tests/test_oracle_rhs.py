@@ -10,6 +10,7 @@ import pytest
 import sympy as sp
 
 import synth
+from conftest import golden
 from oracle import Oracle
 
 RU = 8.31446261815324
@@ -273,12 +274,34 @@ def exact_riemann(rl, ul, pl, rr, ur, pr, g, xi):
 
 
 def test_exact_riemann_solver_textbook_values():
-    """Toro's Test 1 star state: p* = 0.30313, u* = 0.92745."""
-    o = exact_riemann(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4, np.array([0.92745 - 1e-4, 0.92745 + 1e-4]))
-    assert o[2, 0] == pytest.approx(0.30313, rel=1e-4)
-    assert o[1, 0] == pytest.approx(0.92745, rel=1e-4)
-    assert o[0, 0] == pytest.approx(0.42632, rel=1e-4)
-    assert o[0, 1] == pytest.approx(0.26557, rel=1e-4)
+    """Toro's Test 1 star state (tests/golden/sod_toro_test1.csv)."""
+    ref = {k: float(v) for k, v in golden("sod_toro_test1.csv")}
+    us = ref["u_star"]
+    o = exact_riemann(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4, np.array([us - 1e-4, us + 1e-4]))
+    assert o[2, 0] == pytest.approx(ref["p_star"], rel=1e-4)
+    assert o[1, 0] == pytest.approx(us, rel=1e-4)
+    assert o[0, 0] == pytest.approx(ref["rho_star_left"], rel=1e-4)
+    assert o[0, 1] == pytest.approx(ref["rho_star_right"], rel=1e-4)
+
+
+def test_vortex_and_grid_follow_the_paper_setups():
+    """The isentropic-vortex generator and the skewed grid use the set-up
+    the paper prints (tests/golden/paper_convergence_setups.csv): the exact
+    solution's defaults, and the initial field's amplitudes checked against
+    the printed formulas at a few points."""
+    import inspect
+    P = {(t, k): float(v) for t, k, v in golden("paper_convergence_setups.csv")}
+    d = inspect.signature(synth.vortex_exact).parameters
+    for k in ("beta", "alpha", "r0", "gamma", "u0", "v0", "T0", "L"):
+        assert d[k].default == P[("vortex", k)], k
+    assert inspect.signature(synth.skewed_grid).parameters["beta"].default == P[("skewed_grid", "beta_grid")]
+    # printed velocity: u = beta/(2 pi) exp(alpha (1 - r^2/r0^2)) y + u0, v likewise with -x
+    b, a, r0 = P[("vortex", "beta")], P[("vortex", "alpha")], P[("vortex", "r0")]
+    for x, y in ((0.1, -0.2), (0.4, 0.3), (-0.7, 0.05)):
+        f = np.exp(a * (1 - (x * x + y * y) / r0 ** 2))
+        _, u, v, _, _ = synth.vortex_exact(np.array([x]), np.array([y]))
+        assert u[0] == pytest.approx(b / (2 * np.pi) * f * y + P[("vortex", "u0")], rel=1e-14)
+        assert v[0] == pytest.approx(-b / (2 * np.pi) * f * x + P[("vortex", "v0")], rel=1e-14)
 
 
 def _run_sod(n, t_end=3.0e-4):
