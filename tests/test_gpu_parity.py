@@ -8,6 +8,7 @@ import torch
 import synth
 from conftest import flux_floor, normwise, normwise_state, rhs_close
 from gpu_util import both, dev, gpu_cells, gpu_rhs, host, sub_window
+from oracle import Oracle
 from paper_2202_02319_amd import htr
 
 pytestmark = pytest.mark.gpu
@@ -180,3 +181,39 @@ def test_full_size_rhs_sampled(which):
         xi_max = max(float(np.max(case.grid.xin[a])) for a in range(3) if n[a] > 1)
         ok, ratio = rhs_close(got[:, flat][:, inner], ref, flux_floor(Uw, p, xi_max, o.ns), rel=RHS_TOL)
         assert ok, (trial, ratio, normwise(got[:, flat][:, inner], ref))
+
+
+@pytest.mark.parametrize("what", ["nan", "negative_rho", "newton", "hot", "cold"])
+def test_device_errors_match_the_oracle(what):
+    """A bad cell (NaN, rho <= 0, an energy the Newton iteration cannot
+    reach, a temperature outside [Tmin, Tmax]) is latched on the device and
+    reported by htr_check with the error the oracle returns for the same
+    state; the report clears the status, so the next good call passes.  The
+    kernels run to completion on such input (bounded Newton iteration)."""
+    from oracle import OracleError
+    names = {4: "ENONFINITE", 5: "ENEWTON", 6: "ETRANGE"}
+    case = _case(CASES[0][1])
+    q, ns = 17, case.mech.ns
+    if what in ("hot", "cold"):
+        case.T = case.T.copy()
+        case.T[q] = 7000.0 if what == "hot" else 150.0
+    o, g = both(case)
+    U = o.prim_to_cons()
+    if what == "nan":
+        U[2, q] = np.nan
+    elif what == "negative_rho":
+        U[:ns, q] = -np.abs(U[:ns, q])
+    elif what == "newton":
+        U[ns + 3, q] *= 6.0
+    T = case.T.copy()
+    T[q] = 1500.0                      # the Newton guess
+    with pytest.raises(OracleError) as oe:
+        o.rhs(U, T.copy())
+    expect = names[oe.value.code]
+    out = torch.empty((o.nv, o.N), dtype=torch.float64, device="cuda")
+    htr.htr_rhs(g, dev(U), dev(T), 0.0, case.laser, out)
+    with pytest.raises(htr.HTRError, match=expect):
+        htr.htr_check(g)
+    clean = _case(CASES[0][1])
+    htr.htr_rhs(g, dev(Oracle(clean).prim_to_cons()), dev(clean.T), 0.0, clean.laser, out)
+    htr.htr_check(g)
