@@ -55,3 +55,47 @@ def test_tile_shape_check_on_the_host():
     for n, s, why in bad:
         assert lib.htr_tile_shape_check(i3(*n), i3(*s)) == _lib.HTR_EINVAL, (n, s)
         assert why in lib.htr_last_error(), (s, lib.htr_last_error())
+
+
+def test_curvilinear_lattice_checked_before_device_work():
+    """htr_create_curvilinear rejects an invalid grid descriptor before it
+    touches the device: NULL arguments, non-finite coordinates, an inactive
+    axis whose period is not along its own coordinate (or another period
+    with a component along it), and linearly dependent periods."""
+    import ctypes as C
+    import numpy as np
+    lib = _lib.load()
+    out = C.c_void_p()
+    md = _lib.htr_mech_desc()
+    sc = _lib.htr_scheme(cfl=0.5, theta_c=0.1, psi_c=0.05, teno_CT=1e-5, flags=0)
+
+    def desc(n, P, xyz=None):
+        g = _lib.htr_curv_grid_desc()
+        N = n[0] * n[1] * n[2]
+        arr = np.zeros(3 * N) if xyz is None else xyz
+        g._keep = arr
+        g.xyz = arr.ctypes.data_as(_lib._dp)
+        for a in range(3):
+            g.n[a] = n[a]
+            for c in range(3):
+                g.period[a][c] = P[a][c]
+        return g
+    create = lib.htr_create_curvilinear
+    assert create(C.byref(md), None, C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
+    assert create(C.byref(md), C.byref(desc((2, 2, 2), np.eye(3))), C.byref(sc), None) == _lib.HTR_EINVAL
+    bad_xyz = np.zeros(24)
+    bad_xyz[5] = np.nan
+    g = desc((2, 2, 2), np.eye(3), bad_xyz)
+    assert create(C.byref(md), C.byref(g), C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
+    assert b"finite" in lib.htr_last_error()
+    P = np.eye(3)
+    P[2, 0] = 0.5                        # inactive z period leaning into x
+    assert create(C.byref(md), C.byref(desc((4, 3, 1), P)), C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
+    assert b"inactive axis 2" in lib.htr_last_error()
+    P = np.eye(3)
+    P[0, 2] = 0.5                        # x period with a z component, z inactive
+    assert create(C.byref(md), C.byref(desc((4, 3, 1), P)), C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
+    P = np.array([[1.0, 0, 0], [2.0, 0, 0], [0, 0, 1.0]])   # dependent periods
+    assert create(C.byref(md), C.byref(desc((4, 3, 2), P)), C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
+    assert b"linearly dependent" in lib.htr_last_error()
+    assert not out.value
