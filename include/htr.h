@@ -153,8 +153,16 @@ typedef struct {
  * uniform flow is preserved to rounding.  Every single-grid entry point
  * works on it (htr_rhs, htr_cells, htr_stable_dt, htr_rk3_step); the tape,
  * the adjoint and the tiling/autotune calls return HTR_EUNSUPPORTED.
- * Errors: HTR_EINVAL for an invalid lattice or a node where det(d x / d xi)
- * is not positive. */
+ * The host arrays are copied; the context owns, besides the rectilinear
+ * context's scratch, 22 N doubles of geometry (metric terms, face metric
+ * terms, coordinates) and (10 ns + 36) N doubles of per-stage scratch.
+ * Creation blocks: it runs the metric kernels and checks J on the host.
+ * On such a grid the laser centre is a physical position, the Gaussian is
+ * summed over the lattice images, and cell volumes (J objective) are 1/J.
+ * Errors: HTR_EINVAL for NULL arguments, non-finite coordinates or periods,
+ * an invalid lattice (see the descriptor) or a node where det(d x / d xi)
+ * is not positive; these checks other than the last precede any device
+ * work. */
 htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid_desc* grid,
                                   const htr_scheme* scheme, htr_ctx** out);
 
@@ -326,9 +334,13 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
 /* As htr_check, for the ensemble's status word. */
 htr_status htr_batch_check(htr_batch* b, void* stream);
 /* Per member, the largest value of a packed per-cell field (device [Ntot],
- * e.g. T_io) into max_dev[m] (device [nmem]); with accumulate != 0,
- * max_dev[m] = max(max_dev[m], that).  For ensemble workflows such as the
- * ignition-energy search (Sec. 6: ignition judged by the peak temperature). */
+ * member-major as the batch packs T_io) into max_dev[m] (device [nmem],
+ * caller-owned); with accumulate != 0, max_dev[m] = max(max_dev[m], that),
+ * so repeated calls track a running peak.  NaN entries are ignored by the
+ * maximum (htr_batch_check reports non-finite states).  Asynchronous on
+ * stream; HTR_EINVAL for NULL pointers.  For ensemble workflows such as the
+ * ignition-energy search (Sec. 6: the minimum laser energy for ignition,
+ * judged here by the peak temperature). */
 htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_dev, int accumulate,
                                 void* stream);
 
