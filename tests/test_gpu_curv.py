@@ -3,8 +3,8 @@ equations): the HIP path through the C interface against the oracle on the
 same seeded inputs, normwise per row (max|a-b|/max|b|): metric terms,
 per-cell quantities and the RHS <= 1e-12, steps <= 1e-9.  Grids: a wavy
 grid (every metric term varies along every axis), a rotated lattice, the
-skewed grid of the convergence tests; ragged sizes, a 2-D case, short
-periods that wrap the stencils more than once, 12 species.  At the
+skewed grid of the convergence tests; ragged sizes, 2-D and 1-D cases,
+short periods that wrap the stencils more than once, 12 species.  At the
 benchmark's size (128^3 wavy grid) the checks are properties that hold at
 any size: free-stream preservation and discrete conservation."""
 import numpy as np
@@ -27,6 +27,7 @@ CASES = [
     ("2d", dict(n=(17, 11, 1), ns=5, nr=4, seed=23)),
     ("tiny-wrap", dict(n=(4, 5, 3), ns=4, nr=3, seed=25)),
     ("ns12", dict(n=(10, 6, 5), ns=12, nr=30, seed=26)),
+    ("1d", dict(n=(37, 1, 1), ns=3, nr=1, seed=24)),
 ]
 GRIDS = ["wavy", "rotated", "skewed"]
 
@@ -36,6 +37,8 @@ def _grid(kind, n, d):
         return synth.wavy_grid(n, d, amp=0.25, seed=7)
     if kind == "skewed":
         return synth.skewed_grid(n, d, beta=0.2)
+    if n[1] == 1 and n[2] == 1:   # 1-D: a rotation would tilt the inactive axes; a scaled lattice instead
+        return synth.affine_grid(n, d, np.diag([1.3, 1.0, 1.0]))
     R = synth.rotation(0.3, -0.5, 0.9) if n[2] > 1 else synth.rotation(0.0, 0.0, 0.6)
     return synth.affine_grid(n, d, R)
 
