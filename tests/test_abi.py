@@ -99,3 +99,65 @@ def test_curvilinear_lattice_checked_before_device_work():
     assert create(C.byref(md), C.byref(desc((4, 3, 2), P)), C.byref(sc), C.byref(out)) == _lib.HTR_EINVAL
     assert b"linearly dependent" in lib.htr_last_error()
     assert not out.value
+
+
+def test_create_rejects_bad_descriptors_before_device_work():
+    """htr_create validates the mechanism, the grid and the scheme on the
+    host before any device call: empty or oversized mechanisms (ns = 0,
+    ns > HTR_MAX_NS, nr > HTR_MAX_NR), missing tables, an empty axis,
+    non-positive metrics or periods, and invalid scheme parameters."""
+    import ctypes as C
+    import numpy as np
+    lib = _lib.load()
+    keep = []
+
+    def dp(a):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        keep.append(a)
+        return a.ctypes.data_as(_lib._dp)
+
+    def ip(a):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        keep.append(a)
+        return a.ctypes.data_as(_lib._ip)
+
+    def mech(ns=1, nr=0, tables=True, Tmin=200.0, Tmax=6000.0):
+        m = _lib.htr_mech_desc()
+        m.ns, m.nr = ns, nr
+        if tables:
+            m.W, m.nasa7 = dp(np.full(max(ns, 1), 0.029)), dp(np.tile([3.5, 0, 0, 0, 0, 0, 0], max(ns, 1)))
+            m.lj_sigma, m.lj_epsk = dp(np.full(max(ns, 1), 3.6e-10)), dp(np.full(max(ns, 1), 100.0))
+            m.lnA, m.beta, m.Ea = dp(np.zeros(max(nr, 1))), dp(np.zeros(max(nr, 1))), dp(np.zeros(max(nr, 1)))
+            m.nu_f, m.nu_r = ip(np.zeros(max(nr, 1) * max(ns, 1))), ip(np.zeros(max(nr, 1) * max(ns, 1)))
+        m.Tmin, m.Tmax = Tmin, Tmax
+        return m
+
+    def grid(n=(4, 3, 2), xi=1e4, L=1e-3):
+        g = _lib.htr_grid_desc()
+        for a in range(3):
+            g.n[a] = n[a]
+            g.xnode[a] = dp(np.arange(max(n[a], 1)) * 1e-4)
+            g.xi_node[a] = dp(np.full(max(n[a], 1), xi))
+            g.xi_face[a] = dp(np.full(max(n[a], 1), xi))
+            g.L[a] = L
+        return g
+
+    def scheme(cfl=0.5, flags=0):
+        return _lib.htr_scheme(cfl=cfl, theta_c=0.1, psi_c=0.05, teno_CT=1e-5, flags=flags)
+
+    out = C.c_void_p()
+
+    def create(m, g, s):
+        return lib.htr_create(C.byref(m), C.byref(g), C.byref(s), C.byref(out))
+    assert create(mech(ns=0), grid(), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(ns=_lib.HTR_MAX_NS + 1), grid(), scheme()) == 7       # HTR_EUNSUPPORTED
+    assert create(mech(nr=_lib.HTR_MAX_NR + 1), grid(), scheme()) == 7
+    assert create(mech(tables=False), grid(), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(Tmin=300.0, Tmax=300.0), grid(), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(), grid(n=(0, 3, 2)), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(), grid(xi=-1.0), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(), grid(L=0.0), scheme()) == _lib.HTR_EINVAL
+    assert create(mech(), grid(), scheme(cfl=0.0)) == _lib.HTR_EINVAL
+    assert create(mech(), grid(), scheme(flags=_lib.HTR_FORCE_CENTRAL | _lib.HTR_FORCE_TENO)) == _lib.HTR_EINVAL
+    assert b"exclusive" in lib.htr_last_error()
+    assert not out.value
