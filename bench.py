@@ -182,6 +182,32 @@ def cpu_baseline(case, seconds_target=15.0):
                       f"{'grid' if kz == nz else 'slab of the grid'}, {el:.1f} s"}
 
 
+def cpu_baseline_curvilinear(n=64, seconds_target=10.0, amp=0.25):
+    """The oracle (test infrastructure) on the curvilinear workload's recipe
+    at n^3 (the Taylor-Green state on a wavy grid): repeated right-hand-side
+    evaluations of the whole grid for about seconds_target seconds (the
+    metric set-up is not timed)."""
+    from oracle import Oracle
+    import synth
+    c2 = synth.case_c2(n=n)
+    grid = synth.wavy_grid(c2.grid.n, c2.grid.spacing(), amp=amp, seed=11)
+    case = synth.Case("tgv-curv", c2.mech, grid, c2.Y, c2.T, c2.p, c2.vel, flags=c2.flags)
+    o = Oracle(case)
+    U = o.prim_to_cons()
+    T = case.T.copy()
+    t0 = time.perf_counter()
+    o.rhs(U, T, t=0.0)
+    one = time.perf_counter() - t0
+    reps = max(1, int(round(seconds_target / one)))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        o.rhs(U, T, t=0.0)
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": reps * grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} RHS evaluations (one stage each) of the {n}^3 wavy-grid Taylor-Green state, {el:.1f} s"}
+
+
 def ensemble_measure(steps, warm=1, sizes=None):
     """The 64-member ensemble (N^3 members, N uniform on {32, 40, ..., 96}
     unless `sizes` gives the N of each member; perturbed deposition energy,
@@ -467,6 +493,8 @@ def main():
     if args.curv_steps > 0:
         torch.cuda.empty_cache()
         out["curvilinear"] = curvilinear_measure(args.curv_steps)
+        if not args.no_cpu_baseline:
+            out["curvilinear"]["cpu_baseline"] = cpu_baseline_curvilinear()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     if args.calib_copy:
