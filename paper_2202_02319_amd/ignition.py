@@ -8,12 +8,13 @@ each round is ONE batched ensemble, with one launch per kernel over all
 members and the steps captured in a HIP graph, that holds several energies
 for every search at once (a k-section rather than a bisection):
 
-- round 1 runs `members` energies spaced evenly over [E_lo, E_hi], ends
-  included, which also checks that the bracket holds the transition;
-- later rounds run `members` interior energies of the current bracket, so a
-  bracket shrinks by (members - 1) in the first round and by (members + 1)
-  in each one after it (one interior energy per round would be the paper's
-  bisection).
+- the first search iteration runs `members` energies spaced evenly over
+  [E_lo, E_hi], ends included, which also checks that the bracket holds the
+  transition;
+- later iterations run `members` interior energies of the current bracket,
+  so a bracket shrinks by (members - 1) in the first iteration and by
+  (members + 1) in each one after it (one interior energy per iteration
+  would be the paper's bisection).
 
 A member ignites when its peak temperature over the run exceeds T_ign
 (tracked on the device by the library's per-member maximum kernel every
