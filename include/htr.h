@@ -5,16 +5,15 @@
  *
  * Paper: Maeda et al., "An integrated heterogeneous computing framework for
  * ensemble simulations of laser-induced ignition", arXiv 2202.02319.
- *   - conserved state, fluxes, sources: Sec. 5.1, eqs. (1)-(3); closure eq. (4)
+ *   - conserved state, fluxes, sources: Methods › Solver, eqs. (1)-(3); closure eq. (4)
  *   - transport: Wilke viscosity, heat flux eq. (5), diffusion velocity
  *     eq. (6) with mixture-averaged (Bird) and binary (Hirschfelder) D
- *   - chemistry: finite-rate reversible Arrhenius reactions (Sec. 5.1,
- *     "Combustion chemistry")
+ *   - chemistry: finite-rate reversible Arrhenius reactions (Methods › Solver)
  *   - discretisation: conservative finite differences with TENO6 / central
  *     convective fluxes, second-order central diffusive fluxes, SSP-RK3
- *     (Sec. 5.2, "Numerical method"); grid metrics of the mapped equations
- *     (Sec. 5.2) in their rectilinear form
- *   - laser energy source q_L: Sec. 6.3.1, eq. (laser-qs)
+ *     (Methods › Numerical method); grid metrics of the mapped equations
+ *     (Methods › Numerical method) in their rectilinear form
+ *   - laser energy source q_L: Methods › Diffusion flame › Physical model and numerical setup, eq. (laser-qs)
  *
  * Conventions shared by every entry point
  *   - Units are SI.  All floating-point data are IEEE double.
@@ -65,17 +64,17 @@ typedef enum {
 #define HTR_MAX_SIDE 3         /* distinct species on one side of a reaction */
 
 /* scheme flags */
-#define HTR_CHEM_OFF      1u   /* no chemical source (the paper's inert stage, Sec. 6.4.1) */
+#define HTR_CHEM_OFF      1u   /* no chemical source (the paper's inert stage, Methods › Model rocket combustor › Physical model) */
 #define HTR_VISC_OFF      2u   /* no diffusive fluxes                                      */
 #define HTR_FORCE_CENTRAL 4u   /* central flux on every face                               */
 #define HTR_FORCE_TENO    8u   /* TENO6 on every face                                      */
 #define HTR_WENO3Z       16u   /* WENO3-Z instead of TENO6 where the scheme captures shocks
-                                  (Sec. 5.2's alternative; no adjoint: HTR_EUNSUPPORTED)    */
+                                  (Methods › Numerical method's alternative; no adjoint: HTR_EUNSUPPORTED)    */
 
 typedef struct htr_ctx htr_ctx;
 typedef struct htr_batch htr_batch;
 
-/* Mechanism tables (HOST pointers, copied by htr_create).  Sec. 5.1. */
+/* Mechanism tables (HOST pointers, copied by htr_create).  Methods › Solver. */
 typedef struct {
   int32_t ns, nr;
   const double* W;          /* [ns] molar masses, kg/mol                           */
@@ -133,7 +132,7 @@ typedef struct {
 htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, const htr_scheme* scheme,
                       htr_ctx** out);
 
-/* General curvilinear periodic grid (HOST pointers, copied), Sec. 5.2: the
+/* General curvilinear periodic grid (HOST pointers, copied), Methods › Numerical method: the
  * equations mapped to a uniform index space (spacing 1) with U~ = U/J and
  * F~_d = (d xi_d / d x) . (F, G, H) / J, J = det(d xi / d x).
  * xyz[3][N]: node coordinates x, y, z, node (i, j, k) at i + n0 (j + n1 k).
@@ -171,7 +170,11 @@ htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid
  * (the same at face i+1/2 along d).  Asynchronous on stream.  HTR_EINVAL on
  * a rectilinear context. */
 htr_status htr_grid_metrics(htr_ctx* ctx, double* mt, double* mf, void* stream);
-/* Waits for the context's streams to drain and frees it.  NULL is HTR_EINVAL. */
+/* Waits for the work this context enqueued (an event recorded on every
+ * stream an entry point was given; not the whole device) and frees it.
+ * Work enqueued while the caller captured a stream into a graph is not
+ * tracked: the caller synchronises its graph launches first.  NULL is
+ * HTR_EINVAL. */
 htr_status htr_destroy(htr_ctx* ctx);
 /* Replace the scheme flags of an existing context. */
 htr_status htr_set_flags(htr_ctx* ctx, uint32_t flags);
@@ -184,7 +187,7 @@ htr_status htr_prim_to_cons(htr_ctx* ctx, const double* Y, const double* T, cons
                             const double* vel, double* U, void* stream);
 
 /* One right-hand side evaluation dUdt = L(U, t) (eqs. 1-3 in the mapped
- * conservative form of Sec. 5.2): hybrid TENO6/central convective fluxes,
+ * conservative form of Methods › Numerical method): hybrid TENO6/central convective fluxes,
  * second-order diffusive fluxes, chemistry and laser sources.
  *   U      [nv][N] in
  *   T_io   [N] in/out: Newton starting guess in, converged T out
@@ -209,7 +212,7 @@ htr_status htr_stable_dt(htr_ctx* ctx, const double* U, double* T_io, double* dt
 /* Bytes of caller-owned work memory htr_rk3_step needs (two stage states). */
 size_t htr_work_bytes(const htr_ctx* ctx);
 
-/* One SSP-RK3 step in Shu-Osher form (Gottlieb et al. 2001, Sec. 5.2):
+/* One SSP-RK3 step in Shu-Osher form (Gottlieb et al. 2001, Methods › Numerical method):
  *   U1 = U + dt L(U, t); U2 = 3/4 U + 1/4 (U1 + dt L(U1, t+dt));
  *   U <- 1/3 U + 2/3 (U2 + dt L(U2, t+dt/2)).
  *   U          [nv][N] in/out (device)
@@ -244,8 +247,8 @@ htr_status htr_timing_read(htr_ctx* ctx, double* ms, int64_t* launches);
  * Discrete adjoint (reverse mode), for the time-integrated heat release
  * J = sum_steps dt sum_k b_k sum_cells dV HRR(U^(k), t_k) and the parameters
  * theta = (E, centre x, centre y, centre z, ln A_1 .. ln A_nr) of the laser
- * kernel (Sec. 6.3.1) and of the Arrhenius rates (Sec. 5.1).  The paper
- * obtains sensitivities from ensembles of forward runs (Sec. 2); this is the
+ * kernel (Methods › Diffusion flame › Physical model and numerical setup) and of the Arrhenius rates (Methods › Solver).  The paper
+ * obtains sensitivities from ensembles of forward runs (Results › Ensemble simulation); this is the
  * reverse-mode alternative.  Discrete switches (hybrid sensor, TENO
  * cut-offs, argmax of the Lax-Friedrichs speed, Newton iteration count) are
  * frozen: the derivative is that of the scheme with those switches fixed,
@@ -292,7 +295,7 @@ htr_status htr_rk3_step_adjoint(htr_ctx* ctx, const double* Un, const double* st
 /* ------------------------------------------------------------------------
  * Ensembles: many independent grids (members) sharing the context's
  * mechanism and scheme, advanced together (the paper's ensemble workflow,
- * Sec. 2 and Sec. 6: samples with perturbed laser energy, position and
+ * Results › Ensemble simulation, and Application examples: samples with perturbed laser energy, position and
  * rates).  Member m owns cells [off_m, off_m + N_m) of packed arrays: a
  * [rows][N] field of the member starts at base + rows * off_m.  Each member
  * has its own uniform periodic grid, laser kernel, ln A offsets, time, step
@@ -310,6 +313,8 @@ typedef struct {
  * Descriptors are HOST memory, copied.  Errors: HTR_EINVAL (nmem < 1, bad
  * member), HTR_ENOMEM, HTR_EDEVICE. */
 htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* members, htr_batch** out);
+/* Waits for the ensemble's own work (as htr_destroy) and its graph replays,
+ * then frees it.  The context must outlive its ensembles. */
 htr_status htr_batch_destroy(htr_batch* b);
 /* Total packed cells; if offsets (HOST, nmem + 1 entries) is non-NULL it
  * receives the member cell offsets (offsets[nmem] = total). */
@@ -326,8 +331,8 @@ size_t htr_batch_work_bytes(const htr_batch* b);
  * compute_dt each member's dt is its own stable step, as htr_rk3_step).
  * t_dev, dt_dev, J_dev (nullable) are device [nmem].  With use_graph != 0
  * the nsteps steps are captured once into a HIP graph (re-captured when any
- * pointer argument, nsteps or compute_dt changes) and replayed with one
- * graph launch per call. */
+ * pointer argument, nsteps, compute_dt or the context's scheme (flags,
+ * thresholds, CFL) changes) and replayed with one graph launch per call. */
 htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* t_dev, double* dt_dev,
                                  int compute_dt, int nsteps, double* work, double* J_dev, int use_graph,
                                  void* stream);
@@ -339,7 +344,7 @@ htr_status htr_batch_check(htr_batch* b, void* stream);
  * so repeated calls track a running peak.  NaN entries are ignored by the
  * maximum (htr_batch_check reports non-finite states).  Asynchronous on
  * stream; HTR_EINVAL for NULL pointers.  For ensemble workflows such as the
- * ignition-energy search (Sec. 6: the minimum laser energy for ignition,
+ * ignition-energy search (Application examples › Ignition of a diffusion flame › Ensemble and data analysis: the minimum laser energy for ignition,
  * judged here by the peak temperature). */
 htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_dev, int accumulate,
                                 void* stream);

@@ -8,16 +8,16 @@
 //
 // Paper: Maeda et al., "An integrated heterogeneous computing framework for
 // ensemble simulations of laser-induced ignition" (arXiv 2202.02319).
-//   governing equations            Sec. 5.1 "Governing equations", eqs. (1)-(3)
+//   governing equations            Methods › Solver, eqs. (1)-(3)
 //   ideal-gas closure              eq. (4)
-//   Wilke viscosity, NASA c_p      Sec. 5.1, text after eq. (4)
+//   Wilke viscosity, NASA c_p      Methods › Solver, text after eq. (4)
 //   heat flux                      eq. (5)
 //   diffusion velocity             eq. (6), Bird mixture-averaged D_s with
 //                                  Hirschfelder binary D_ij
-//   finite-rate Arrhenius chem.    Sec. 5.1 "Combustion chemistry"
+//   finite-rate Arrhenius chem.    Methods › Solver (chemistry)
 //   conservative FD, TENO6, 2nd-order central diffusion, SSP-RK3
-//                                  Sec. 5.2 "Numerical method"
-//   laser source q_L               Sec. 6.3.1, eq. (laser-qs)
+//                                  Methods › Numerical method
+//   laser source q_L               Methods › Diffusion flame › Physical model and numerical setup, eq. (laser-qs)
 //
 // Structure: every step is its own loop, in the order the method defines it:
 //   1. per cell: primitives (Newton for T), transport, chemistry, laser;
@@ -94,7 +94,7 @@ struct Case {
   double L[3];
   double theta_c, psi_c, CT, cfl;
   unsigned flags;
-  // general curvilinear grid (Sec. 5.2, mapped equations): node coordinates,
+  // general curvilinear grid (Methods › Numerical method, mapped equations): node coordinates,
   // the lattice periods, and the metric terms derived from them
   bool curv = false;
   std::vector<double> X[3];          // X[c][q]: coordinate c of node q
@@ -334,7 +334,7 @@ static S laser_q(const Case& C, const Params<S>& P, int i, int j, int k, double 
 }
 
 // ------------------------------------------------------ curvilinear grids
-// Sec. 5.2: the equations are mapped from (x, y, z) to a uniform index space
+// Methods › Numerical method: the equations are mapped from (x, y, z) to a uniform index space
 // (xi, eta, zeta), with U~ = U/J and F~ = (xi_x F + xi_y G + xi_z H)/J along
 // each index direction, J = det(d xi / d x).  The index spacing is 1.
 //
@@ -473,7 +473,7 @@ static S laser_q_curv(const Case& C, const Params<S>& P, long long q, double t) 
 
 // ----------------------------------------------------------------- WENO3-Z
 // Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges 2013), the
-// paper's alternative shock-capturing scheme (Sec. 5.2), from f_{i-1}, f_i,
+// paper's alternative shock-capturing scheme (Methods › Numerical method), from f_{i-1}, f_i,
 // f_{i+1} = f[1..3] of the six-point face stencil: candidates on {i-1, i} and
 // {i, i+1} with optimal weights 1/3 and 2/3, smoothness indicators the
 // squared first differences, global indicator tau = |beta_0 - beta_1|,

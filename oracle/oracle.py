@@ -4,6 +4,7 @@ TEST INFRASTRUCTURE ONLY.  Host (numpy) arrays in, host arrays out.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -40,47 +41,84 @@ def build_oracle(force: bool = False) -> str:
 _lib = None
 
 
+def _bind(path):
+    """Opens a compiled oracle library and declares its C signatures."""
+    L = C.CDLL(path)
+    L.orc_case_new.restype = C.c_void_p
+    L.orc_case_new.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ip, C.c_double,
+                               C.c_double, _ip, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                               C.c_double, C.c_uint]
+    L.orc_case_free.argtypes = [C.c_void_p]
+    L.orc_case_set_curvilinear.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_metrics.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_set_flags.argtypes = [C.c_void_p, C.c_uint]
+    L.orc_prim_to_cons.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
+    L.orc_cells.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp]
+    L.orc_rhs.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
+    L.orc_stable_dt.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_rk3_step.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, _dp, C.c_void_p, _dp]
+    L.orc_rk3_tangent.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, C.c_void_p,
+                                  C.c_void_p, _dp, _dp]
+    L.orc_rhs_tangent.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p, _dp, _dp,
+                                  _dp, _dp]
+    L.orc_rates.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_teno6_detail.restype = C.c_double
+    L.orc_teno6_detail.argtypes = [_dp, C.c_double, _dp]
+    L.orc_thermo.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp]
+    L.orc_teno6.restype = C.c_double
+    L.orc_teno6.argtypes = [_dp, C.c_double]
+    L.orc_weno3z.restype = C.c_double
+    L.orc_weno3z.argtypes = [_dp]
+    for f in ("orc_omega22", "orc_omega11"):
+        getattr(L, f).restype = C.c_double
+        getattr(L, f).argtypes = [C.c_double]
+    L.orc_mu_species.restype = C.c_double
+    L.orc_mu_species.argtypes = [C.c_void_p, C.c_int, C.c_double]
+    L.orc_D_binary.restype = C.c_double
+    L.orc_D_binary.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double]
+    L.orc_cell_volume.restype = C.c_double
+    L.orc_cell_volume.argtypes = [C.c_void_p, C.c_longlong]
+    return L
+
+
 def _load():
     global _lib
     if _lib is None:
         build_oracle()
-        L = C.CDLL(LIB)
-        L.orc_case_new.restype = C.c_void_p
-        L.orc_case_new.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ip, C.c_double,
-                                   C.c_double, _ip, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
-                                   C.c_double, C.c_uint]
-        L.orc_case_free.argtypes = [C.c_void_p]
-        L.orc_case_set_curvilinear.argtypes = [C.c_void_p, _dp, _dp]
-        L.orc_metrics.argtypes = [C.c_void_p, _dp, _dp, _dp]
-        L.orc_set_flags.argtypes = [C.c_void_p, C.c_uint]
-        L.orc_prim_to_cons.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
-        L.orc_cells.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp]
-        L.orc_rhs.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
-        L.orc_stable_dt.argtypes = [C.c_void_p, _dp, _dp, _dp]
-        L.orc_rk3_step.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, _dp, C.c_void_p, _dp]
-        L.orc_rk3_tangent.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, C.c_void_p,
-                                      C.c_void_p, _dp, _dp]
-        L.orc_rhs_tangent.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p, _dp, _dp,
-                                      _dp, _dp]
-        L.orc_rates.argtypes = [C.c_void_p, _dp, _dp, _dp]
-        L.orc_teno6_detail.restype = C.c_double
-        L.orc_teno6_detail.argtypes = [_dp, C.c_double, _dp]
-        L.orc_thermo.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp]
-        L.orc_teno6.restype = C.c_double
-        L.orc_teno6.argtypes = [_dp, C.c_double]
-        L.orc_weno3z.restype = C.c_double
-        L.orc_weno3z.argtypes = [_dp]
-        for f in ("orc_omega22", "orc_omega11"):
-            getattr(L, f).restype = C.c_double
-            getattr(L, f).argtypes = [C.c_double]
-        L.orc_mu_species.restype = C.c_double
-        L.orc_mu_species.argtypes = [C.c_void_p, C.c_int, C.c_double]
-        L.orc_D_binary.restype = C.c_double
-        L.orc_D_binary.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double]
-        L.orc_cell_volume.restype = C.c_double
-        L.orc_cell_volume.argtypes = [C.c_void_p, C.c_longlong]
-        _lib = L
+        _lib = _bind(LIB)
     return _lib
+
+
+def build_variant(replacements, out_dir, name="liboracle_variant.so"):
+    """Compiles a copy of the oracle source with the given (old, new) text
+    replacements, each of which must match exactly once, into out_dir and
+    returns the library's path.  Used only by the tests that plant a mistake
+    in the oracle to show that its pins catch it."""
+    src = open(SRC).read()
+    for old, new in replacements:
+        if src.count(old) != 1:
+            raise ValueError(f"replacement target occurs {src.count(old)} times: {old!r}")
+        src = src.replace(old, new)
+    os.makedirs(out_dir, exist_ok=True)
+    cpp = os.path.join(out_dir, name.replace(".so", ".cpp"))
+    with open(cpp, "w") as fh:
+        fh.write(src)
+    lib = os.path.join(out_dir, name)
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                           "-fPIC", "-shared", "-o", lib, cpp])
+    return lib
+
+
+@contextlib.contextmanager
+def use_library(path):
+    """Oracle objects created inside the block use the library at path."""
+    global _lib
+    prev = _load()
+    _lib = _bind(path)
+    try:
+        yield
+    finally:
+        _lib = prev
 
 
 def _ptr(a):

@@ -89,6 +89,7 @@ htr_status htr_rhs_adjoint(htr_ctx* c, const double* U, double* T_io, double t, 
                            const double* dlnA_dev, const double* lam, double s, double h, double* Ubar_acc,
                            double* pbar_acc, double* adj_work, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (c->scheme.flags & HTR_WENO3Z)
     return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for rectilinear grids");
@@ -106,6 +107,7 @@ htr_status htr_rk3_step_adjoint(htr_ctx* c, const double* Un, const double* stag
                                 double dt, const htr_laser* laser, const double* dlnA_dev, double Jbar,
                                 double* Ubar, double* pbar_acc, double* adj_work, const void* tape, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (c->scheme.flags & HTR_WENO3Z)
     return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for rectilinear grids");

@@ -144,7 +144,8 @@ htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* m
 
 htr_status htr_batch_destroy(htr_batch* b) {
   if (!b) return fail(HTR_EINVAL, "batch is NULL");
-  hipDeviceSynchronize();
+  b->fence.wait();                      // this ensemble's work on the callers' streams
+  if (b->gstream) hipStreamSynchronize(b->gstream);   // and its graph replays
   drop_graph(b);
   if (b->gstream) hipStreamDestroy(b->gstream);
   if (b->ev_in) hipEventDestroy(b->ev_in);
@@ -160,6 +161,7 @@ htr_status htr_batch_destroy(htr_batch* b) {
 htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_dev, int accumulate,
                                 void* stream) {
   if (!b || !field || !max_dev) return fail(HTR_EINVAL, "NULL pointer");
+  Marked mk_(&b->fence, stream);
   HIP_OK(launch_member_max(b->dmem, b->nmem, field, max_dev, accumulate, (hipStream_t)stream));
   return HTR_OK;
 }
@@ -178,6 +180,7 @@ size_t htr_batch_work_bytes(const htr_batch* b) {
 htr_status htr_batch_prim_to_cons(htr_batch* b, const double* Y, const double* T, const double* p,
                                   const double* vel, double* U, void* stream) {
   if (!b) return fail(HTR_EINVAL, "batch is NULL");
+  Marked mk_(&b->fence, stream);
   if (!Y || !T || !p || !vel || !U) return fail(HTR_EINVAL, "NULL field pointer");
   Ctx C = bview(b);
   HIP_OK(launch_prim_to_cons(C.ns, C.M, C.mem, C.nmem, C.nblocks, Y, T, p, vel, U, (hipStream_t)stream));
@@ -187,6 +190,7 @@ htr_status htr_batch_prim_to_cons(htr_batch* b, const double* Y, const double* T
 htr_status htr_rhs_batched(htr_batch* b, const double* U, double* T_io, const double* t_dev, double* dUdt,
                            double* hrr, void* stream) {
   if (!b) return fail(HTR_EINVAL, "batch is NULL");
+  Marked mk_(&b->fence, stream);
   if (!U || !T_io || !t_dev || !dUdt) return fail(HTR_EINVAL, "NULL pointer");
   if (U == dUdt) return fail(HTR_EINVAL, "dUdt must not alias U");
   Ctx C = bview(b);
@@ -201,6 +205,7 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
                                  int compute_dt, int nsteps, double* work, double* J_dev, int use_graph,
                                  void* stream) {
   if (!b) return fail(HTR_EINVAL, "batch is NULL");
+  Marked mk_(&b->fence, stream);
   if (!U || !T_io || !t_dev || !dt_dev || !work) return fail(HTR_EINVAL, "NULL pointer");
   if (nsteps < 0) return fail(HTR_EINVAL, "nsteps must be >= 0");
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
@@ -214,7 +219,12 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
     return HTR_OK;
   }
   const void* key[7] = {U, T_io, t_dev, dt_dev, work, J_dev, b->ctx->dM};
-  bool same = b->exec && b->key_steps == nsteps && b->key_cdt == compute_dt &&
+  // the scheme (flags, thresholds) is baked into the captured kernel arguments
+  const htr_scheme& sc = b->ctx->scheme;
+  const bool same_scheme = sc.flags == b->key_scheme.flags && sc.cfl == b->key_scheme.cfl &&
+                           sc.theta_c == b->key_scheme.theta_c && sc.psi_c == b->key_scheme.psi_c &&
+                           sc.teno_CT == b->key_scheme.teno_CT;
+  bool same = b->exec && b->key_steps == nsteps && b->key_cdt == compute_dt && same_scheme &&
               std::memcmp(key, b->key, sizeof key) == 0;
   if (!same) {
     drop_graph(b);
@@ -240,6 +250,7 @@ htr_status htr_rk3_steps_batched(htr_batch* b, double* U, double* T_io, double* 
     std::memcpy(b->key, key, sizeof key);
     b->key_steps = nsteps;
     b->key_cdt = compute_dt;
+    b->key_scheme = sc;
   }
   // order the replay after the caller's stream and the caller's stream after it
   HIP_OK(hipEventRecord(b->ev_in, s));

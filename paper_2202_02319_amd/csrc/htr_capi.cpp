@@ -193,6 +193,31 @@ void ws_free(Workspace& w) {
   w = Workspace{};
 }
 
+void Fence::mark(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  for (auto& p : ev)
+    if (p.first == s) {
+      hipEventRecord(p.second, s);
+      return;
+    }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+  hipEventRecord(e, s);
+  ev.emplace_back(s, e);
+}
+hipError_t Fence::wait() {
+  hipError_t r = hipSuccess;
+  for (auto& p : ev) {
+    hipError_t e = hipEventSynchronize(p.second);
+    if (e != hipSuccess && r == hipSuccess) r = e;
+  }
+  return r;
+}
+Fence::~Fence() {
+  for (auto& p : ev) hipEventDestroy(p.second);
+}
+
 hipEvent_t Timer::get() {
   if (!pool.empty()) {
     hipEvent_t e = pool.back();
@@ -205,6 +230,7 @@ hipEvent_t Timer::get() {
 }
 void Timer::clear() {
   for (auto& r : recs) {
+    hipEventSynchronize(r.b);   // the pair may still be pending on its stream
     pool.push_back(r.a);
     pool.push_back(r.b);
   }
@@ -552,6 +578,7 @@ htr_status htr_create_curvilinear(const htr_mech_desc* mech, const htr_curv_grid
 
 htr_status htr_grid_metrics(htr_ctx* c, double* mt, double* mf, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!c->curv) return fail(HTR_EINVAL, "not a curvilinear context");
   if (!mt || !mf) return fail(HTR_EINVAL, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
@@ -562,7 +589,7 @@ htr_status htr_grid_metrics(htr_ctx* c, double* mt, double* mf, void* stream) {
 
 htr_status htr_destroy(htr_ctx* c) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
-  hipDeviceSynchronize();
+  c->fence.wait();   // this context's own work, on every stream it was given
   hipFree(c->dM);
   hipFree(c->dgrid);
   hipFree(c->dmem);
@@ -584,6 +611,7 @@ htr_status htr_set_flags(htr_ctx* c, uint32_t flags) {
 htr_status htr_prim_to_cons(htr_ctx* c, const double* Y, const double* T, const double* p, const double* vel,
                             double* U, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!Y || !T || !p || !vel || !U) return fail(HTR_EINVAL, "NULL field pointer");
   Ctx C = view(c);
   HIP_OK(launch_prim_to_cons(C.ns, C.M, C.mem, C.nmem, C.nblocks, Y, T, p, vel, U, (hipStream_t)stream));
@@ -593,6 +621,7 @@ htr_status htr_prim_to_cons(htr_ctx* c, const double* Y, const double* T, const 
 htr_status htr_rhs(htr_ctx* c, const double* U, double* T_io, double t, const htr_laser* laser, double* dUdt,
                    double* hrr, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!U || !T_io || !dUdt) return fail(HTR_EINVAL, "NULL field pointer");
   if (U == dUdt) return fail(HTR_EINVAL, "dUdt must not alias U");
   if (!std::isfinite(t)) return fail(HTR_EINVAL, "t must be finite");
@@ -610,6 +639,7 @@ htr_status htr_rhs(htr_ctx* c, const double* U, double* T_io, double t, const ht
 htr_status htr_cells(htr_ctx* c, const double* U, double* T_io, double t, const htr_laser* laser, double* out,
                      void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!U || !T_io || !out) return fail(HTR_EINVAL, "NULL field pointer");
   htr_status st = check_laser(laser);
   if (st) return st;
@@ -631,6 +661,7 @@ htr_status htr_cells(htr_ctx* c, const double* U, double* T_io, double t, const 
 
 htr_status htr_stable_dt(htr_ctx* c, const double* U, double* T_io, double* dt_dev, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!U || !T_io || !dt_dev) return fail(HTR_EINVAL, "NULL pointer");
   Ctx C = view(c);
   CallArgs a{};
@@ -648,6 +679,7 @@ htr_status htr_rk3_step(htr_ctx* c, double* U, double* T_io, double* t_dev, doub
                         const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
                         void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!U || !T_io || !t_dev || !dt_dev || !work) return fail(HTR_EINVAL, "NULL pointer");
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
   htr_status st = check_laser(laser);
@@ -667,6 +699,7 @@ htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev
                               const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
                               void* tape, void* stream) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  Marked mk_(&c->fence, stream);
   if (!U || !T_io || !t_dev || !dt_dev || !work || !tape) return fail(HTR_EINVAL, "NULL pointer");
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for rectilinear grids");
@@ -680,8 +713,7 @@ htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev
 
 htr_status htr_timing(htr_ctx* c, int enable) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
-  HIP_OK(hipDeviceSynchronize());
-  c->timer.clear();
+  c->timer.clear();   // waits for each recorded launch's closing event
   c->timer.on = enable != 0;
   return HTR_OK;
 }

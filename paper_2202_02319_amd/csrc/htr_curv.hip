@@ -1,4 +1,4 @@
-// General curvilinear grids (Sec. 5.2, the mapped equations): metric terms,
+// General curvilinear grids (Methods › Numerical method, the mapped equations): metric terms,
 // sensor, mapped face fluxes and the stage update of a single-grid context.
 //
 // The equations are mapped to a uniform index space with U~ = U/J and

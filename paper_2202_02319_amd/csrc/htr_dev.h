@@ -77,7 +77,7 @@ struct Member {
   const double* dlnA;         // nullable [nr]
 };
 
-// General curvilinear grid of a single-grid context (Sec. 5.2, the mapped
+// General curvilinear grid of a single-grid context (Methods › Numerical method, the mapped
 // equations): metric terms at nodes and faces, node coordinates, lattice.
 struct CurvGeom {
   const double* mt;    // [10][N]: (d xi_d / d x_c) / J at row 3d + c; J at row 9

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdarg>
+#include <utility>
 #include <vector>
 
 #include "htr.h"
@@ -31,6 +32,25 @@ struct Workspace {
   double* blkred = nullptr;       // [2][nblocks]
   unsigned* status = nullptr;
   double* scal = nullptr;         // [2][nmem] scratch scalars
+};
+
+// The streams a context or an ensemble has enqueued work on, each with an
+// event recorded after the last such work.  Destroying the object waits on
+// these events only, not on the whole device.  Work enqueued under stream
+// capture is not tracked (the caller owns the graph and its launches).
+struct Fence {
+  std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+  void mark(hipStream_t s);
+  hipError_t wait();
+  ~Fence();
+};
+
+// Marks the fence when an entry point returns, after it has enqueued its work.
+struct Marked {
+  Fence* f;
+  hipStream_t s;
+  Marked(Fence* f_, void* s_) : f(f_), s((hipStream_t)s_) {}
+  ~Marked() { f->mark(s); }
 };
 
 // Timing classes (the order of htr_timing_read's arrays).
@@ -133,6 +153,7 @@ struct htr_ctx {
   int grid = 0;                    // persistent grid (0: off)
   htr::Workspace ws;
   htr::Timer timer;
+  htr::Fence fence;
   // curvilinear grid (htr_create_curvilinear); L above then holds the
   // distances between lattice planes (laser image counts)
   bool curv = false;
@@ -156,12 +177,14 @@ struct htr_batch {
   int grid = 0;                    // persistent grid (0: off)
   htr::Workspace ws;
   htr::Timer timer;
+  htr::Fence fence;
   hipStream_t gstream = nullptr;   // capture/replay stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* key[7] = {};
   int key_steps = -1, key_cdt = -1;
+  htr_scheme key_scheme{};         // scheme (flags, thresholds) baked into the captured kernels
 };
 
 

@@ -3,10 +3,10 @@
 // chemistry, laser source, heat release, stable-step limit), plus the
 // dilatation sensor and the per-member reductions.
 //
-// Paper (arXiv 2202.02319) Sec. 5.1: eqs. (1)-(4), Wilke viscosity, NASA
+// Paper (arXiv 2202.02319) Methods › Solver: eqs. (1)-(4), Wilke viscosity, NASA
 // thermodynamics, heat flux eq. (5), diffusion velocity eq. (6) with Bird
 // mixture-averaged and Hirschfelder binary diffusivities, Arrhenius
-// chemistry; Sec. 6.3.1 eq. (laser-qs) for q_L.
+// chemistry; Methods › Diffusion flame › Physical model and numerical setup eq. (laser-qs) for q_L.
 //
 // One thread per cell.  The species count is a compile-time parameter so
 // that every per-species array lives in registers; species concentrations

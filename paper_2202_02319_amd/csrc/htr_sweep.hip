@@ -3,9 +3,9 @@
 // second-order diffusive flux, plus the chemistry and laser sources, fused
 // with the SSP-RK3 stage combination (or written as dU/dt).
 //
-// Paper (arXiv 2202.02319) Sec. 5.2: conservative finite differences of the
+// Paper (arXiv 2202.02319) Methods › Numerical method: conservative finite differences of the
 // mapped equations (rectilinear metrics), TENO6 for the inviscid fluxes,
-// second-order central differences for the diffusive fluxes; Sec. 5.1 eqs.
+// second-order central differences for the diffusive fluxes; Methods › Solver eqs.
 // (1)-(3), (5), (6) for the flux vectors.
 //
 // Two tiled kernels per stage, one block per 256-cell tile: k_conv (sources

@@ -1,5 +1,5 @@
 """Minimum ignition energy by a bracketing search on the batched ensemble
-path: the paper's ensemble workflow over the deposited laser energy (Sec. 6,
+path: the paper's ensemble workflow over the deposited laser energy (Application examples › Ignition of a diffusion flame › Ensemble and data analysis,
 ensemble and data analysis): for each laser duration, an interval [a, b] is
 tightened such that energy a does not ignite and b does.
 

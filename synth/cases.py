@@ -1,8 +1,8 @@
 """Seeded synthetic workloads: grids, primitive initial fields, laser kernels
 and ensemble tables.
 
-The paper's applications (the 2-D diffusion flame of Sec. 6.3 and the model
-combustor of Sec. 6.4) need mechanisms, geometry and data that are not
+The paper's applications (the 2-D diffusion flame of Application examples › Ignition of a diffusion flame and the model
+combustor of Application examples › Ignition of a model combustor) need mechanisms, geometry and data that are not
 available; these generators stand in for them with the shapes, sizes and
 structure of the five benchmark workloads:
 
@@ -142,7 +142,7 @@ def rotation(ax, ay, az):
 
 
 def skewed_grid(n, d, beta=0.2, origin=None) -> CurvGrid:
-    """Periodic skewed grid of the paper's convergence tests (Sec. 5.3.1):
+    """Periodic skewed grid of the paper's convergence tests (Methods › Solver Performance Analysis › Accuracy):
     each coordinate is displaced by beta L/2 times the sine of the other
     active coordinates (averaged over them),
         x_c = xi_c + beta (L_c / 2) mean_{c' != c} sin(2 pi xi_c' / L_c'),
@@ -193,7 +193,7 @@ def wavy_grid(n, d, amp=0.25, seed=0) -> CurvGrid:
 
 @dataclass
 class Laser:
-    """Gaussian deposition kernel (Sec. 6.3.1): energy, centre, spatial and
+    """Gaussian deposition kernel (Methods › Diffusion flame › Physical model and numerical setup): energy, centre, spatial and
     temporal support, delay."""
     E: float = 0.0
     center: tuple = (0.0, 0.0, 0.0)
@@ -417,7 +417,7 @@ def sod_case(n=200, W=0.02897, axis=0) -> Case:
 
 
 def vortex_case(n=32, L=10.0) -> Case:
-    """Isentropic vortex (Sec. 5.3.1 set-up) on a Cartesian periodic grid in
+    """Isentropic vortex (Methods › Solver Performance Analysis › Accuracy set-up) on a Cartesian periodic grid in
     non-dimensional units: one species with R_u/W = 1 and gamma = 1.4, so
     that p = rho T; beta = 5, alpha = 1/2, r0 = 0.5, (u0, v0, T0) = (1, 1, 1)."""
     mech = single_species(RU, 3.5, Tmin=1e-3, Tmax=1e3)
@@ -438,7 +438,7 @@ def vortex_case_curv(grid: CurvGrid, L=10.0) -> Case:
 
 def tgv2d_case(grid, L=2 * np.pi, u0=1.0, rho0=1.0, gamma=1.4, sigma=1.5e-11) -> Case:
     """Two-dimensional Taylor-Green vortex of the paper's viscous accuracy
-    test (Sec. 5.3.1) in non-dimensional units: one species with R_u/W = 1
+    test (Methods › Solver Performance Analysis › Accuracy) in non-dimensional units: one species with R_u/W = 1
     and gamma = 1.4, u = u0 sin(kx) cos(ky), v = -u0 cos(kx) sin(ky),
     p = p0 + rho0 u0^2/4 (cos 2kx + cos 2ky) (k = 2 pi / L), rho = rho0,
     Mach number u0 / c0 = 1e-2 / sqrt(gamma).  Fields at the physical node

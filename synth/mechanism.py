@@ -1,6 +1,6 @@
 """Seeded synthetic reaction mechanisms.
 
-The paper's methane mechanisms (Sec. 5.1, "Combustion chemistry") are not
+The paper's methane mechanisms (Methods › Solver) are not
 available, so every mechanism here is drawn from a seed: species are small
 H/O(/N) formulas, reactions are every element-balanced exchange with one or
 two molecules on each side, and the thermodynamic, transport and Arrhenius

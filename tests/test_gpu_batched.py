@@ -212,3 +212,31 @@ def test_full_size_ensemble():
     htr.htr_check(g)
     assert np.array_equal(host(Ug), b.unpack(U2h, ctx.nv, ml))
     assert float(host(Jg)[0]) == float(host(J)[ml])
+
+
+def test_graph_replay_follows_scheme_changes(ens):
+    """The captured graph bakes the scheme into its kernel arguments: after
+    htr_set_flags the next replay must run the new scheme, bit for bit as
+    eager stepping does (a stale graph would keep the old one)."""
+    ctx, b, U, T, t, dt, J, work = _batch_setup(ens)
+    U0, T0 = U.clone(), T.clone()
+    results = {}
+    for flags in (0, synth.FORCE_TENO, synth.FORCE_CENTRAL | synth.CHEM_OFF, 0):
+        ctx.set_flags(flags)
+        runs = []
+        for graph in (True, False):
+            U.copy_(U0)
+            T.copy_(T0)
+            t.zero_()
+            dt.zero_()
+            J.zero_()
+            htr.htr_rk3_steps_batched(b, U, T, t, dt, 1, 2, work, J, use_graph=graph)
+            htr.htr_batch_check(b)
+            runs.append((host(U), host(J)))
+        assert np.array_equal(runs[0][0], runs[1][0]), flags
+        assert np.array_equal(runs[0][1], runs[1][1]), flags
+        results.setdefault(flags, []).append(runs[0][0])
+    # the schemes really differ, and going back to a scheme reproduces it
+    assert not np.array_equal(results[0][0], results[synth.FORCE_TENO][0])
+    assert not np.array_equal(results[0][0], results[synth.FORCE_CENTRAL | synth.CHEM_OFF][0])
+    assert np.array_equal(results[0][0], results[0][1])

@@ -1,4 +1,4 @@
-"""GPU parity on general curvilinear grids (Sec. 5.2, the mapped
+"""GPU parity on general curvilinear grids (Methods › Numerical method, the mapped
 equations): the HIP path through the C interface against the oracle on the
 same seeded inputs, normwise per row (max|a-b|/max|b|): metric terms,
 per-cell quantities and the RHS <= 1e-12, steps <= 1e-9.  Grids: a wavy

@@ -1,6 +1,6 @@
 """Brute force: the convective right-hand side of tiny periodic grids
 written out straight-line in 40-digit arithmetic (mpmath), apart from the
-oracle's assembly, and compared with the oracle (Sec. 5.2: conservative
+oracle's assembly, and compared with the oracle (Methods › Numerical method: conservative
 finite differences; the central six-point flux, or TENO6 / WENO3-Z on a
 local Lax-Friedrichs split; the hybrid switch).
 

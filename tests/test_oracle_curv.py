@@ -1,6 +1,6 @@
-"""Pins of the oracle on general curvilinear grids (paper Sec. 5.2, the
+"""Pins of the oracle on general curvilinear grids (paper Methods › Numerical method, the
 mapped equations with U~ = U/J and F~ = (xi_x F + xi_y G + xi_z H)/J; the
-convergence set-up of Sec. 5.3.1 on a skewed grid).
+convergence set-up of Methods › Solver Performance Analysis › Accuracy on a skewed grid).
 
 - the metric terms equal the closed-form cofactors of an affine map exactly,
   and converge at sixth order to the analytic ones of a smooth map;
@@ -219,7 +219,7 @@ def test_laser_integrates_to_the_energy_on_a_sheared_lattice(n, sigma):
 
 @pytest.mark.slow
 def test_isentropic_vortex_on_the_skewed_grid():
-    """The paper's vortex-advection test on a skewed grid (Sec. 5.3.1 set-up,
+    """The paper's vortex-advection test on a skewed grid (Methods › Solver Performance Analysis › Accuracy set-up,
     beta = 0.2, t = 0.05): with sixth-order metrics the hybrid scheme keeps
     high order, as on the Cartesian grid; measured order 3.9 from N = 32 to
     64 (pre-asymptotic) and 7.1 from 64 to 128, error 6.5e-6 at 128."""
@@ -245,7 +245,7 @@ def test_isentropic_vortex_on_the_skewed_grid():
 
 @pytest.mark.parametrize("kind,floor", [("cartesian", 1.8), ("skewed", 1.8)])
 def test_viscous_taylor_green_second_order(kind, floor):
-    """The paper's viscous accuracy test (Sec. 5.3.1): the 2-D Taylor-Green
+    """The paper's viscous accuracy test (Methods › Solver Performance Analysis › Accuracy): the 2-D Taylor-Green
     vortex with L = 2 pi, mu = 1 (Re0 = L), Ma0 = 1e-2/sqrt(gamma), error at
     t = 0.05 (tests/golden/paper_convergence_setups.csv), on the Cartesian
     grid and on the skewed grid, against the decaying incompressible

@@ -1,4 +1,4 @@
-"""Pins of the oracle's per-cell physics (paper Sec. 5.1): NASA thermo
+"""Pins of the oracle's per-cell physics (paper Methods › Solver): NASA thermo
 identities, the ideal-gas closure (eq. 4), Chapman-Enskog transport against
 the practical-unit textbook formulas, Wilke/Eucken special cases, mass and
 element conservation of the chemistry, detailed balance at equilibrium, and

@@ -1,4 +1,4 @@
-"""Pins of the oracle's assembled right-hand side (paper Sec. 5.2, eqs.
+"""Pins of the oracle's assembled right-hand side (paper Methods › Numerical method, eqs.
 1-3 in conservative finite-difference form): free-stream preservation,
 discrete conservation, the closed-form modified wavenumber of the six-point
 flux difference (central and TENO on smooth data), the viscous shear wave,
@@ -354,7 +354,7 @@ def test_stable_dt_closed_form():
 
 @pytest.mark.parametrize("force,min_order", [(0, 5.5), (synth.FORCE_TENO, 3.0)])
 def test_isentropic_vortex_convergence(force, min_order):
-    """The paper's vortex-advection accuracy test (Sec. 5.3.1 set-up, on a
+    """The paper's vortex-advection accuracy test (Methods › Solver Performance Analysis › Accuracy set-up, on a
     Cartesian grid, t = 0.05): the hybrid TENO6/central scheme converges at
     sixth order (observed >= 5.5 between N = 64 and 128).  TENO forced on
     every face trims candidate stencils on the barely resolved core at these

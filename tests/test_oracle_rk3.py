@@ -1,5 +1,5 @@
 """Pins of the oracle's time integration (SSP-RK3 in Shu-Osher form,
-Gottlieb et al. 2001, cited in Sec. 5.2), of the time-integrated heat
+Gottlieb et al. 2001, cited in Methods › Numerical method), of the time-integrated heat
 release and of the forward-mode tangent."""
 import numpy as np
 import pytest

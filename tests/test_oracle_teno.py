@@ -2,7 +2,7 @@
 independently (sympy): candidate stencils and smoothness indicators as the
 Jiang-Shu integrals of interpolating polynomials, the sixth-order
 scale-separation measure, and the ENO cut-off on discontinuities.
-Scheme: TENO6 (Fu et al. 2016), cited by the paper in Sec. 5.2."""
+Scheme: TENO6 (Fu et al. 2016), cited by the paper in Methods › Numerical method."""
 import numpy as np
 import pytest
 import sympy as sp

@@ -1,4 +1,4 @@
-"""WENO3-Z, the paper's alternative shock-capturing reconstruction (Sec. 5.2,
+"""WENO3-Z, the paper's alternative shock-capturing reconstruction (Methods › Numerical method,
 Don & Borges's third-order WENO-Z), in the oracle: pinned by what the
 scheme must satisfy, not by its formulas: exactness on linear data,
 convergence to the optimal third-order upwind-biased flux on smooth data,
@@ -86,7 +86,7 @@ def test_sod_with_weno3z_everywhere():
 
 @pytest.mark.slow
 def test_isentropic_vortex_with_weno3z_everywhere():
-    """WENO3-Z on every face converges on the vortex (Sec. 5.3.1 set-up).
+    """WENO3-Z on every face converges on the vortex (Methods › Solver Performance Analysis › Accuracy set-up).
     With the global indicator's power 1 it loses order at the smooth extrema
     of the split fluxes, and these grids are pre-asymptotic: between N = 64
     and 256 the observed orders are about 1.2-1.5 (max norm) and 1.6-1.7
@@ -113,7 +113,7 @@ def test_isentropic_vortex_with_weno3z_everywhere():
 
 
 def test_weno3z_against_teno6_in_the_hybrid_scheme():
-    """The paper's comparison of its two schemes on the vortex (Sec. 5.3.1):
+    """The paper's comparison of its two schemes on the vortex (Methods › Solver Performance Analysis › Accuracy):
     WENO3-Z about ten times TENO6's error, WENO3-Z third order.  Taken in
     the hybrid scheme (each at the faces the sensor flags, the central flux
     elsewhere): at N = 32 the measured ratio is 8.9 and WENO3-Z converges
