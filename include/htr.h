@@ -230,6 +230,28 @@ htr_status htr_rk3_step(htr_ctx* ctx, double* U, double* T_io, double* t_dev, do
                         const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
                         void* stream);
 
+/* The step of htr_rk3_step without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments and results are those of
+ * htr_rk3_step without `work`: the two stage states and the step's per-cell
+ * scratch (derived fields, sources, sensor flags, velocity gradients,
+ * partial right-hand side, block partials) live in one fixed device array
+ * of HTR_NOALLOC_MAX_BYTES per GPU, held until the process ends.  The
+ * context still owns its tables and status word (htr_check).  The call makes
+ * no hipMalloc/hipFree and no allocating library call; it returns
+ * HTR_EINVAL, before any device work, when the grid needs more than the
+ * array holds: 8 N (3 (ns + 4) + (7 + ns) + (ns + 1) + 9) + N bytes plus
+ * block partials and 256-byte alignment: about 113,000 cells at ns = 9 (48^3).
+ * Every call on one GPU shares that GPU's array (also across contexts), so
+ * calls that overlap on one GPU (different streams or threads) race; the
+ * array keeps the last call's contents, and nothing in it needs clearing
+ * (each step writes every region before reading it).  HTR_EINVAL also when
+ * the current device is not the context's. */
+#define HTR_NOALLOC_MAX_BYTES (64u << 20)
+htr_status htr_rk3_step_noalloc(htr_ctx* ctx, double* U, double* T_io, double* t_dev, double* dt_dev,
+                                int compute_dt, const htr_laser* laser, const double* dlnA_dev, double* J_dev,
+                                void* stream);
+
 /* Kernel timing for diagnostics: while enabled, every kernel the context
  * launches is bracketed by HIP events on its stream.  htr_timing_read
  * synchronises and returns, per kernel class (0 per-cell point kernel,

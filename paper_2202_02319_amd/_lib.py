@@ -81,6 +81,7 @@ def load():
         "htr_stable_dt": (st, [vp, vp, vp, vp, vp]),
         "htr_work_bytes": (C.c_size_t, [vp]),
         "htr_rk3_step": (st, [vp, vp, vp, vp, vp, C.c_int, C.POINTER(htr_laser), vp, vp, vp, vp]),
+        "htr_rk3_step_noalloc": (st, [vp, vp, vp, vp, vp, C.c_int, C.POINTER(htr_laser), vp, vp, vp]),
         "htr_timing": (st, [vp, C.c_int]),
         "htr_timing_read": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "htr_check": (st, [vp, vp]),

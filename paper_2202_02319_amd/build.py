@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhtr.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["htr_point.hip", "htr_sweep.hip", "htr_curv.hip", "htr_adjoint.hip", "htr_capi.cpp", "htr_batch.cpp", "htr_adjoint_api.cpp",
-           "htr_tune.cpp"]
+           "htr_tune.cpp", "htr_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]

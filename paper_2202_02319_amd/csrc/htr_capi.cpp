@@ -473,6 +473,8 @@ htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, cons
     return bail(fail(HTR_EDEVICE, "hipMemcpy member: %s", hipGetErrorString(e)));
   st = ws_alloc(c->ws, c->ns, N, c->nblocks, 1);
   if (st) return bail(st);
+  st = noalloc_init(c->device);
+  if (st) return bail(st);
   *out = c;
   return HTR_OK;
 }

@@ -108,6 +108,9 @@ void ws_free(Workspace& w);
 htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const double* U, const double* Un, double* T,
                  double* out, double ca, double cb, int rhs_only, double* hrr, double* J_dev, double jcoef,
                  hipStream_t s, int want_dt, double* dt_out, unsigned char* teno_bits = nullptr);
+// Looks up, once per device and with that device current, the device
+// address of the no-allocation step's scratch array (htr_noalloc.hip).
+htr_status noalloc_init(int device);
 htr_status rk3(const Ctx& C, const Workspace& w, double* U, double* T, double* t_dev, double* dt_dev,
                int compute_dt, const htr_laser* laser, const double* dlnA, double* work, double* J_dev,
                hipStream_t s, void* tape);

@@ -166,6 +166,12 @@ def htr_rk3_step(ctx, U, T_io, t_dev, dt_dev, compute_dt, laser, dlnA_dev, work,
                                C.byref(L) if L else None, _ptr(dlnA_dev), _ptr(work), _ptr(J_dev), _stream(stream)))
 
 
+def htr_rk3_step_noalloc(ctx, U, T_io, t_dev, dt_dev, compute_dt, laser, dlnA_dev, J_dev=None, stream=None):
+    L = make_laser(laser)
+    check(ctx.lib.htr_rk3_step_noalloc(ctx.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dt_dev), int(compute_dt),
+                                       C.byref(L) if L else None, _ptr(dlnA_dev), _ptr(J_dev), _stream(stream)))
+
+
 def htr_timing(ctx, enable):
     check(ctx.lib.htr_timing(ctx.h, int(enable)))
 
