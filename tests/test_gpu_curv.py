@@ -4,7 +4,8 @@ same seeded inputs, normwise per row (max|a-b|/max|b|): metric terms,
 per-cell quantities and the RHS <= 1e-12, steps <= 1e-9.  Grids: a wavy
 grid (every metric term varies along every axis), a rotated lattice, the
 skewed grid of the convergence tests; ragged sizes, 2-D and 1-D cases,
-short periods that wrap the stencils more than once, 12 species.  At the
+short periods that wrap the stencils more than once, 12 species, and grids
+that span several ragged face tiles along every direction.  At the
 benchmark's size (128^3 wavy grid) the checks are properties that hold at
 any size: free-stream preservation and discrete conservation."""
 import numpy as np
@@ -95,6 +96,55 @@ def test_rhs_parity(name, kw, kind, flags):
     err = normwise(got, ref)
     assert err.max() <= RHS_TOL, err
     assert normwise(hrr_g[None], hrr_o[None]).max() <= RHS_TOL
+
+
+# grids spanning several ragged face tiles along every stencil direction of
+# the convective face kernel (64 x 4 faces per tile along x, 16 x 16 along y
+# and z): 70 = 64 + 6, 37 = 2 x 16 + 5, 21 = 16 + 5, 130 = 2 x 64 + 2, 40 = 2 x 16 + 8
+MULTITILE = [("3d-70x37x21", (70, 37, 21)), ("2d-130x40", (130, 40, 1))]
+
+
+@pytest.mark.parametrize("flags", [0, synth.FORCE_TENO, synth.VISC_OFF | synth.FORCE_TENO])
+@pytest.mark.parametrize("kind", ["wavy", "skewed"])
+@pytest.mark.parametrize("name,n", MULTITILE)
+def test_rhs_parity_multitile(name, n, kind, flags):
+    """The RHS where face tiles meet along every direction (halo values staged
+    by neighbouring tiles) against the oracle, normwise per row <= 1e-12."""
+    case = _case(dict(n=n, ns=5, nr=4, seed=27), kind, flags)
+    o, g = both(case)
+    U = o.prim_to_cons()
+    ref, hrr_o = o.rhs(U, case.T.copy(), t=2e-8, want_hrr=True)
+    got, T_g, hrr_g = gpu_rhs(g, U, case.T.copy(), 2e-8, case.laser, want_hrr=True)
+    err = normwise(got, ref)
+    assert err.max() <= RHS_TOL, err
+    assert normwise(hrr_g[None], hrr_o[None]).max() <= RHS_TOL
+    if flags == 0:   # the hybrid switch picks both schemes on these grids
+        _, mask = o.rhs(U, case.T.copy(), t=2e-8, want_mask=True)
+        assert 0 < mask.mean() < 1
+
+
+@pytest.mark.parametrize("name,n", MULTITILE)
+def test_steps_multitile(name, n):
+    """Three SSP-RK3 steps with the in-step dt on the multi-tile wavy grids."""
+    case = _case(dict(n=n, ns=5, nr=4, seed=28), "wavy", c1_mech=True)
+    o, g = both(case)
+    U0 = o.prim_to_cons()
+    U, T, t = U0.copy(), case.T.copy(), 0.0
+    for _ in range(3):
+        dt = o.stable_dt(U, T)
+        o.rk3_step(U, T, t, dt)
+        t += dt
+    Ug, Tg = dev(U0), dev(case.T)
+    work = g.new_work()
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    td = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        htr.htr_rk3_step(g, Ug, Tg, td, dtd, 1, case.laser, None, work, None)
+    htr.htr_check(g)
+    assert float(host(td)[0]) == pytest.approx(t, rel=1e-12)
+    c = o.cells(U, T)[2]
+    rho_c = float(U[:o.ns].sum(axis=0).max() * c.max())
+    assert normwise_state(host(Ug), U, o.ns, rho_c).max() <= STEP_TOL
 
 
 @pytest.mark.parametrize("kind", GRIDS)
