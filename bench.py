@@ -9,7 +9,12 @@ stage also reduces the stable dt), the dilatation sensor, and the fused flux
 sweep with the stage update; the time-integrated heat release accumulates on
 the device.  Inputs are seeded synthetic fields resident in HBM.
 
-Prints one JSON line.  `value` = cells x 3 stages x steps / time.
+Prints one JSON line.  `value` = cells x 3 stages x steps / time.  The same
+line carries, under their own keys, the 256x128x128 mixing layer with laser
+deposition over its 100 steps, the 64-member ensemble over 50 steps (one
+captured graph against per-member launches), the 64^3 adjoint workload over
+50 steps (backward/forward time), the 128^3 curvilinear grid, and the
+oracle timed on the host cores (a baseline, not the target).
 """
 from __future__ import annotations
 
@@ -27,50 +32,51 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s
-EXP_WEIGHT = 20                # FP64 operations charged per exp/log (polynomial evaluation)
-
-
 def point_flops_per_cell(ns, nr, laser_on, newton_iters=3):
     """Algorithmic FP64 operations of the per-cell kernel (one stage), from
-    the operation counts of its formulas; each exp/log counts EXP_WEIGHT."""
+    the operation counts of its formulas (+, -, *, /, sqrt = 1, FMA = 2);
+    exponentials, logarithms and powers are not counted here but in
+    point_transcendentals_per_cell."""
     newton = newton_iters * (ns * 25 + 2)
     thermo = ns * 13 + ns * 2 + 8
     transport = ns * 20 + ns * ns * 6 + ns * 5 + (ns * (ns - 1) // 2) * 17 + ns * 2
-    trans_exp = 3 * ns + 4 * (ns * (ns - 1) // 2) + 2
     chem = ns * 21 + nr * (5 + 2 * ns + 2 + 4 + 1 + 2 * ns) + ns * 14
-    chem_exp = 2 * nr + 1
     laser = 30 if laser_on else 0
-    laser_exp = 9 if laser_on else 0
     misc = 40
-    return newton + thermo + transport + chem + laser + misc + EXP_WEIGHT * (trans_exp + chem_exp + laser_exp)
+    return newton + thermo + transport + chem + laser + misc
 
 
-def conv_bytes_per_cell(ns):
-    """Algorithmic HBM bytes of the convective sweep per cell and stage:
-    read U, the per-cell p, c, u, v, w, the sensor byte and the sources
-    (wdot_s, q_L); write the partial right-hand side."""
+def point_transcendentals_per_cell(ns, nr, laser_on):
+    """exp/log/pow evaluations of the per-cell kernel per cell and stage:
+    three per species for mu_s (Omega(2,2) fit), four per pair for D_ij
+    (Omega(1,1) fit), two for the mixture, two per reaction (k_f, K_c)
+    plus ln T, and nine for the laser's Gaussians."""
+    return 3 * ns + 4 * (ns * (ns - 1) // 2) + 2 + 2 * nr + 1 + (9 if laser_on else 0)
+
+
+def sweep_bytes_per_cell(ns):
+    """Algorithmic HBM bytes of the flux sweep (sensor, convective and
+    diffusive flux differences, stage update) per cell and stage, by the
+    item list of the measurement plan: read U (nv), the per-cell fields the
+    fluxes need (p, c, mu, lambda, T, D_s: 5 + ns), the sources (wdot_s,
+    q_L: ns + 1) and, in stages 2-3 (2/3 on average), U^n (nv); write
+    U^(k+1) (nv).  469 B at ns = 9 (the plan's estimate: about 460 B)."""
     nv = ns + 4
-    return 8 * nv + 8 * 5 + 1 + 8 * (ns + 1) + 8 * nv
-
-
-def diff_bytes_per_cell(ns):
-    """Algorithmic HBM bytes of the diffusive sweep with the stage update per
-    cell and stage: read U, u, v, w, mu, lambda, D_s, the nine velocity
-    gradients, T, the partial right-hand side and (stages 2-3, so 2/3 on
-    average) U^n; write the new stage."""
-    nv = ns + 4
-    return 8 * nv + 8 * (5 + ns) + 8 * 9 + 8 + 8 * nv + 8 * nv * 2.0 / 3.0 + 8 * nv
+    return 8 * (nv + (5 + ns) + (ns + 1) + nv * 2.0 / 3.0 + nv)
 
 
 def point_bytes_per_cell(ns):
-    """Read U and T; write T, the per-cell fields and the sources."""
+    """Algorithmic HBM bytes of the per-cell kernel per cell and stage: read
+    U and T; write T, c, mu, lambda, D_s and the sources (the plan's item
+    list: 296 B at ns = 9, about 300 B)."""
     nv = ns + 4
-    return 8 * (nv + 1) + 8 * (1 + (7 + ns) + (ns + 1))
+    return 8 * (nv + 1) + 8 * (1 + 3 + ns + (ns + 1))
 
 
 CSRC = os.path.join(ROOT, "paper_2202_02319_amd", "csrc")
 KERNEL_SOURCES = {
     "k_point": ("htr_point.hip", "htr_dev.h", "htr_flux.h"),
+    "k_sensor": ("htr_point.hip", "htr_dev.h", "htr_flux.h"),
     "k_conv": ("htr_sweep.hip", "htr_dev.h", "htr_flux.h"),
     "k_diff": ("htr_sweep.hip", "htr_dev.h", "htr_flux.h"),
 }
@@ -178,6 +184,7 @@ def cpu_baseline(case, seconds_target=15.0):
     el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": reps * sub.grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{reps} RHS evaluations (one stage each) of a {sub.grid.n[0]}x{sub.grid.n[1]}x{sub.grid.n[2]} "
                       f"{'grid' if kz == nz else 'slab of the grid'}, {el:.1f} s"}
 
@@ -205,6 +212,7 @@ def cpu_baseline_curvilinear(n=64, seconds_target=10.0, amp=0.25):
     el = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": reps * grid.N / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{reps} RHS evaluations (one stage each) of the {n}^3 wavy-grid Taylor-Green state, {el:.1f} s"}
 
 
@@ -368,6 +376,116 @@ def adjoint_measure(nsteps=50, every=10, n=64):
             "dJ_dE": float(gh[0]), "dJ_dcentre": [float(v) for v in gh[1:4]]}
 
 
+def single_measure(case, steps, warmup, autotune=True):
+    """`steps` timed SSP-RK3 steps (in-step CFL dt, J accumulated) of one
+    grid after `warmup` untimed ones, HIP events on the launch stream; then
+    the same number of steps again with per-kernel event timing.  Returns
+    the throughput, the per-kernel launch averages and the roofline of the
+    per-cell kernel and of the flux sweep."""
+    import torch
+    from paper_2202_02319_amd import htr
+    ctx = htr.Context.from_case(case)
+    N = ctx.N
+    U = htr.cons_from_case(ctx, case)
+    T = htr.to_dev(case.T)
+    z = lambda: torch.zeros(1, dtype=torch.float64, device="cuda")  # noqa: E731
+    t_dev, dt_dev, J_dev = z(), z(), z()
+    work = ctx.new_work()
+    laser = case.laser if case.laser.on else None
+    tile, grid = htr.htr_autotune(ctx, U, T.clone(), work) if autotune else htr.htr_get_tiling(ctx)
+
+    U0, T0 = U.clone(), T.clone()
+
+    def step():
+        htr.htr_rk3_step(ctx, U, T, t_dev, dt_dev, 1, laser, None, work, J_dev)
+
+    def restart():
+        # every pass starts from the initial state, so no pass runs the
+        # workload past its configured number of steps
+        U.copy_(U0)
+        T.copy_(T0)
+        t_dev.zero_()
+        J_dev.zero_()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    htr.htr_check(ctx)
+    restart()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    htr.htr_check(ctx)
+    ms = e0.elapsed_time(e1) / steps
+    J_timed = float(J_dev.item())
+    # per-kernel durations, HIP events on the launch stream, the same steps again
+    restart()
+    htr.htr_timing(ctx, 1)
+    for _ in range(steps):
+        step()
+    kt = htr.htr_timing_read(ctx)
+    htr.htr_timing(ctx, 0)
+    htr.htr_check(ctx)
+    ns, nr = case.mech.ns, case.mech.nr
+    avg = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    # the per-cell kernel against the FP64 vector peak (formula FLOPs, the
+    # exponentials counted apart), the flux sweep (sensor + convective +
+    # diffusive kernels, one stage) against HBM with its algorithmic bytes
+    fl = point_flops_per_cell(ns, nr, laser is not None)
+    ach = fl * N / (avg["point"] / 1e3) / 1e12
+    point = {"kernel": "k_point", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "flops_per_cell": fl,
+             "transcendentals_per_cell": point_transcendentals_per_cell(ns, nr, laser is not None),
+             "bytes_per_cell": point_bytes_per_cell(ns), "avg_ms": round(avg["point"], 4)}
+    sweep_ms = avg["sensor"] + avg["conv"] + avg["diff"]
+    bpc = sweep_bytes_per_cell(ns)
+    ach = bpc * N / (sweep_ms / 1e3) / 1e9
+    sweep = {"kernel": "sweep (k_sensor + k_conv + k_diff)", "bound": "hbm", "achieved": round(ach, 1),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+             "bytes_per_cell": round(bpc, 1), "avg_ms": round(sweep_ms, 4),
+             "parts_ms": {"k_sensor": round(avg["sensor"], 4), "k_conv": round(avg["conv"], 4),
+                          "k_diff": round(avg["diff"], 4)}}
+    return {"ctx": ctx, "N": N, "ms": ms, "wall": wall, "value": N * 3 / (ms / 1e3), "tile": tile, "grid": grid,
+            "avg": avg, "kt": kt, "point": point, "sweep": sweep, "J": J_timed}
+
+
+def roofline_of(meas, workload, steps):
+    """The dominant one of the per-cell kernel and the flux sweep (longer
+    per-stage time), with HBM traffic from the committed counter summary."""
+    dom = "sweep" if meas["sweep"]["avg_ms"] >= meas["point"]["avg_ms"] else "point"
+    roof = {k: v for k, v in meas[dom].items() if k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
+    kernels = ("k_sensor", "k_conv", "k_diff") if dom == "sweep" else ("k_point",)
+    tb = [measured_traffic(k, workload) for k in kernels]
+    tb = None if any(b is None for b in tb) else float(sum(tb))
+    roof["traffic"] = round(tb / (meas[dom]["avg_ms"] / 1e3) / 1e9, 1) if tb is not None else None
+    roof["traffic_bytes_per_stage"] = tb
+    roof["avg_ms_per_stage"] = meas[dom]["avg_ms"]
+    roof["point"] = meas["point"]
+    roof["sweep"] = meas["sweep"]
+    roof["kernel_ms"] = {k: round(v, 4) for k, v in meas["avg"].items()}
+    roof["step_ms_by_kernel"] = {k: round(v[0] / steps, 4) for k, v in meas["kt"].items()}
+    return roof
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,7 +494,9 @@ def main():
     ap.add_argument("--workload", choices=["tgv128", "mixing256"], default="tgv128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--ens-steps", type=int, default=5, help="RK3 steps of the ensemble measurement (0: skip)")
+    ap.add_argument("--mix-steps", type=int, default=100,
+                    help="RK3 steps of the 256x128x128 mixing-layer measurement (0: skip)")
+    ap.add_argument("--ens-steps", type=int, default=50, help="RK3 steps of the ensemble measurement (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
     ap.add_argument("--curv-steps", type=int, default=5,
                     help="RK3 steps of the curvilinear-grid measurement (0: skip)")
@@ -391,80 +511,19 @@ def main():
 
     import torch
     import synth
-    from paper_2202_02319_amd import htr
 
     case = synth.case_c2() if args.workload == "tgv128" else synth.case_c3()
-    ctx = htr.Context.from_case(case)
-    N = ctx.N
-    U = htr.cons_from_case(ctx, case)
-    T = htr.to_dev(case.T)
-    t_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    J_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    work = ctx.new_work()
-    laser = case.laser if case.laser.on else None
-    tile, grid = htr.htr_autotune(ctx, U, T.clone(), work) if not args.no_autotune else htr.htr_get_tiling(ctx)
-
-    def step():
-        htr.htr_rk3_step(ctx, U, T, t_dev, dt_dev, 1, laser, None, work, J_dev)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    htr.htr_check(ctx)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    htr.htr_check(ctx)
-    ms = e0.elapsed_time(e1) / args.steps
-    value = N * 3 * args.steps / (ms * args.steps / 1e3)
-
-    # per-kernel durations, HIP events on the launch stream, same steps again
-    htr.htr_timing(ctx, 1)
-    for _ in range(args.steps):
-        step()
-    kt = htr.htr_timing_read(ctx)
-    htr.htr_timing(ctx, 0)
-    htr.htr_check(ctx)
+    meas = single_measure(case, args.steps, args.warmup, autotune=not args.no_autotune)
     ns, nr = case.mech.ns, case.mech.nr
-    avg = {k: (v[0] / max(v[1], 1), v[1]) for k, v in kt.items()}
-    # every main kernel against its own bound; the dominant one is reported
-    kern = {}
-    for k, name, bpc in (("conv", "k_conv", conv_bytes_per_cell(ns)), ("diff", "k_diff", diff_bytes_per_cell(ns))):
-        ach = bpc * N / (avg[k][0] / 1e3) / 1e9
-        kern[k] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_cell": round(bpc, 2)}
-    fl = point_flops_per_cell(ns, nr, laser is not None)
-    ach = fl * N / (avg["point"][0] / 1e3) / 1e12
-    kern["point"] = {"kernel": "k_point", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "flops_per_cell": fl}
-    dom = max(("point", "conv", "diff"), key=lambda k: kt[k][0])
-    roof = {k: v for k, v in kern[dom].items() if k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}
-    tb = measured_traffic(kern[dom]["kernel"], args.workload)
-    roof["traffic"] = round(tb / (avg[dom][0] / 1e3) / 1e9, 1) if tb is not None else None
-    roof["traffic_bytes_per_launch"] = tb
-    roof["kernel_avg_ms"] = round(avg[dom][0], 4)
-    roof["all_kernels"] = kern
-    roof["kernel_ms"] = {k: round(v[0], 4) for k, v in avg.items()}
-    roof["step_ms_by_kernel"] = {k: round(v[0] / args.steps, 4) for k, v in kt.items()}
-
     out = {
         "metric": "FP64 cell-stage updates/s (plain vs batched ensemble); adjoint/forward time",
-        "value": value,
+        "value": meas["value"],
         "unit": "cell-stage updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
-        "wall_s": wall,
+        "ms_per_step": meas["ms"],
+        "wall_s": meas["wall"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -474,13 +533,24 @@ def main():
                                "Mach 0.3, SSP-RK3 with in-step CFL dt"
                    if args.workload == "tgv128" else
                    "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser",
-                   "cells": N, "species": ns, "reactions": nr, "stages_per_step": 3,
-                   "tile": "x".join(map(str, tile)), "persistent_grid": grid},
-        "roofline": roof,
+                   "cells": meas["N"], "species": ns, "reactions": nr, "stages_per_step": 3,
+                   "tile": "x".join(map(str, meas["tile"])), "persistent_grid": meas["grid"]},
+        "roofline": roofline_of(meas, args.workload, args.steps),
     }
-    if args.ens_steps > 0:
-        del U, T, work
+    del meas
+    torch.cuda.empty_cache()
+    if args.mix_steps > 0 and args.workload == "tgv128":
+        c3 = synth.case_c3()
+        m3 = single_measure(c3, args.mix_steps, 2, autotune=not args.no_autotune)
+        out["mixing256"] = {
+            "workload": "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser deposition, "
+                        f"{args.mix_steps} SSP-RK3 steps with in-step CFL dt",
+            "cells": m3["N"], "steps": args.mix_steps, "value": m3["value"], "unit": "cell-stage updates/s",
+            "ms_per_step": m3["ms"], "tile": "x".join(map(str, m3["tile"])), "J": m3["J"],
+            "roofline": roofline_of(m3, "mixing256", args.mix_steps)}
+        del m3
         torch.cuda.empty_cache()
+    if args.ens_steps > 0:
         out["ensemble"] = ensemble_measure(args.ens_steps)
         torch.cuda.empty_cache()
         # small members (N = 12..24): each member alone fills a few CUs, so

@@ -33,6 +33,7 @@ P_ATM = 101325.0
 
 # scheme flags (bit values of the C interfaces)
 CHEM_OFF, VISC_OFF, FORCE_CENTRAL, FORCE_TENO, WENO3Z = 1, 2, 4, 8, 16
+BC_PERIODIC, BC_WALL, BC_INFLOW, BC_OUTFLOW = 0, 1, 2, 3
 
 
 @dataclass
@@ -224,6 +225,11 @@ class Case:
     steps: int = 1
     t0: float = 0.0
     meta: dict = field(default_factory=dict)
+    # boundary type per axis and side (low, high): BC_PERIODIC, BC_WALL,
+    # BC_INFLOW, BC_OUTFLOW; the outflow's far-field pressure and relaxation
+    bc: tuple = ((0, 0), (0, 0), (0, 0))
+    pinf: tuple = ((0.0, 0.0), (0.0, 0.0), (0.0, 0.0))
+    relax: tuple = ((0.0, 0.0), (0.0, 0.0), (0.0, 0.0))
 
 
 def dirichlet_Y(rng, ns, size=None):
@@ -232,6 +238,28 @@ def dirichlet_Y(rng, ns, size=None):
         y = rng.dirichlet(np.ones(ns))
         if y.min() >= 1e-8:
             return y
+
+
+# Fuel and oxidizer streams of the mixing layers carry only the mechanism's
+# stable species: those whose enthalpy constant per unit mass (a6 R_u / W) is
+# at most this in magnitude.  The others (atoms and radicals, whose seeded
+# constants reach ~90 MJ/kg) start at a trace mass fraction.
+STREAM_HF_CAP = 5e6       # J/kg
+STREAM_TRACE = 1e-6
+
+
+def stream_Y(rng, mech: Mechanism):
+    """A fuel or oxidizer stream: a flat Dirichlet draw over all species
+    (dirichlet_Y, same draws), then the species above STREAM_HF_CAP set to
+    STREAM_TRACE and the rest rescaled to sum to one."""
+    y = dirichlet_Y(rng, mech.ns)
+    rad = np.abs(np.asarray(mech.nasa7)[:, 5]) * RU / np.asarray(mech.W) > STREAM_HF_CAP
+    if rad.all():
+        return y
+    y = np.where(rad, 0.0, y)
+    y = y / y.sum() * (1.0 - STREAM_TRACE * rad.sum())
+    y[rad] = STREAM_TRACE
+    return y
 
 
 def nominal_sound_speed(mech: Mechanism, Y, T):
@@ -314,7 +342,8 @@ def case_c2(seed=2, n=128, ns=9, nr=20, mech_seed=MECH_SEED["C2"]) -> Case:
 def mixing_layer(mech: Mechanism, n, dx, ic, noise_rng, *, E_mJ=None, center_shift=(0.0, 0.0, 0.0),
                  E_scale=1.0, YF=None, YO=None) -> tuple:
     """Periodic double mixing layer in y: fuel stream in the middle band,
-    oxidizer outside, tanh profiles of thickness 4 dy, shear dU = 0.5 c0
+    oxidizer outside (each of stable species, stream_Y), tanh profiles of
+    thickness 4 dy, shear dU = 0.5 c0
     with 1% band-limited velocity noise, T = 300 K, p = 1 atm, and a laser
     kernel (radius 8 cells) centred on the lower layer."""
     g = uniform_grid(n, dx)
@@ -323,9 +352,9 @@ def mixing_layer(mech: Mechanism, n, dx, ic, noise_rng, *, E_mJ=None, center_shi
     dl = 4 * dx
     phi = 0.5 * (np.tanh((y - Ly / 4) / dl) - np.tanh((y - 3 * Ly / 4) / dl))
     if YF is None:
-        YF = dirichlet_Y(ic, mech.ns)
+        YF = stream_Y(ic, mech)
     if YO is None:
-        YO = dirichlet_Y(ic, mech.ns)
+        YO = stream_Y(ic, mech)
     Y = phi[None] * YF[:, None, None, None] + (1 - phi[None]) * YO[:, None, None, None]
     T0 = 300.0
     Ym = 0.5 * (YF + YO)
@@ -379,8 +408,8 @@ def ensemble_c4(seed=4, nmem=64, ns=9, nr=20, sizes=None, steps=50, mech_seed=ME
     shifted by U[-10, 10] cells per axis and ln A_j + U[-0.5, 0.5]."""
     _, ic, noise, ens = _streams(seed)
     mech = _mech(ns, nr, mech_seed)
-    YF = dirichlet_Y(ic, mech.ns)
-    YO = dirichlet_Y(ic, mech.ns)
+    YF = stream_Y(ic, mech)
+    YO = stream_Y(ic, mech)
     E_mJ = float(ic.uniform(0.1, 1.0))
     if sizes is None:
         sizes = ens.choice(np.arange(32, 97, 8), size=nmem)
@@ -395,6 +424,21 @@ def ensemble_c4(seed=4, nmem=64, ns=9, nr=20, sizes=None, steps=50, mech_seed=ME
         members.append(Case(f"C4[{m}]", mech, g, Y, T, p, vel, laser=las, steps=steps, meta=meta))
         dlnA.append(dl)
     return Ensemble(mech, members, np.array(dlnA), steps=steps)
+
+
+# Mechanism seed of the ignition-search base case: a 5-species, 4-reaction
+# mechanism whose net heat release turns positive, and grows with the
+# deposited energy, once the laser has heated the layer (the workloads'
+# seeded mechanisms are net endothermic at those temperatures); explicitly
+# stable by the same screen as the workloads.
+IGNITION_MECH_SEED = 15
+
+
+def ignition_base(n=16, mech_seed=IGNITION_MECH_SEED) -> Case:
+    """One n^3 member of the mixing-layer ensemble recipe (first member's
+    perturbations) with the ignition mechanism: the base case of the
+    minimum-ignition-energy search."""
+    return ensemble_c4(nmem=1, sizes=[n], ns=5, nr=4, mech_seed=mech_seed).members[0]
 
 
 # ----------------------------------------------------------------- test cases

@@ -39,6 +39,8 @@ def _stiffness(case, Tmax, dlnA=0.0):
     ("C2", lambda: synth.case_c2(n=32), 1200.0, 0.0),
     ("C3", lambda: synth.case_c3(n=(32, 32, 32)), 2000.0, 0.0),
     ("C4", lambda: synth.case_c3(n=(32, 32, 32)), 2000.0, 0.5),
+    ("ignition", lambda: synth.case_c3(n=(32, 32, 32), ns=5, nr=4, mech_seed=synth.cases.IGNITION_MECH_SEED),
+     2500.0, 0.0),
 ])
 def test_chemistry_explicitly_stable(name, make, Tmax, dlnA):
     case = make()

@@ -1,14 +1,14 @@
 """Ignition-energy search on the batched path: the bracketing logic on the
-host, and on the GPU the search against single-grid runs of the bracket's
-ends."""
+host, and on the GPU the search, judged by the heat released after the
+deposit, against the oracle's runs of the bracket's ends."""
 import numpy as np
 import pytest
-import torch
 
 import synth
 from paper_2202_02319_amd import htr
-from paper_2202_02319_amd.ignition import (initial_stable_dt, min_ignition_energies, narrow, round_energies,
-                                           with_energy)
+from oracle import Oracle
+from paper_2202_02319_amd.ignition import (deposit_end_step, ignited, initial_stable_dt, min_ignition_energies,
+                                           narrow, round_energies, run_members, with_energy)
 
 
 def test_narrow_keeps_the_transition():
@@ -45,60 +45,72 @@ def test_bracket_shrinks_on_a_monotone_response(members):
         assert hi - lo == pytest.approx(width, rel=1e-9)
 
 
-def _base(n=16):
-    """One 16^3 member of the mixing-layer ensemble (its mechanism, mixture
-    and laser kernel)."""
-    return synth.ensemble_c4(nmem=1, sizes=[n]).members[0]
-
-
-def _single_peak(case, nsteps, dt_step, chunk):
-    """Peak T of a single-grid run (same fixed step, same sampling)."""
-    ctx = htr.Context.from_case(case)
-    U = htr.cons_from_case(ctx, case)
-    T = torch.as_tensor(case.T.copy(), device="cuda")
-    t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    dt = torch.full((1,), dt_step, dtype=torch.float64, device="cuda")
-    work = ctx.new_work()
-    peak = float(T.max())
-    for k in range(nsteps):
-        htr.htr_rk3_step(ctx, U, T, t, dt, 0, case.laser, None, work, None)
-        if (k + 1) % chunk == 0 or k + 1 == nsteps:
+def _oracle_run(case, n_d, n_after, dt, chunk):
+    """The oracle's run of one member: J at the deposit end, `chunk` steps
+    before the end and at the end; the peak temperature sampled like the
+    batched run (initial field, then every chunk steps) and the final one."""
+    o = Oracle(case)
+    U = o.prim_to_cons()
+    T = case.T.copy()
+    t, J, peak = 0.0, 0.0, float(T.max())
+    J_d = J_last = None
+    n_tot = n_d + n_after
+    marks = set(range(chunk, n_d, chunk)) | {n_d} | set(n_d + k for k in range(chunk, n_after - chunk, chunk)) \
+        | {n_tot - chunk, n_tot}
+    for n in range(1, n_tot + 1):
+        J = o.rk3_step(U, T, t, dt, J=J)
+        t += dt
+        if n in marks:
             peak = max(peak, float(T.max()))
-    htr.htr_check(ctx)
-    return peak
+        if n == n_d:
+            J_d = J
+        if n == n_tot - chunk:
+            J_last = J
+    return J_d, J, J_last, peak, float(T.max())
 
 
 @pytest.mark.gpu
-def test_search_on_the_batched_path_matches_single_runs():
+def test_search_on_the_batched_path_against_the_oracle():
     """Two searches (laser durations sigma_t and 2 sigma_t) in one ensemble
-    per round: the brackets shrink as designed, the batched peaks equal
-    single-grid runs bit for bit, and the bracket ends run alone fall on
-    either side of the threshold."""
-    b0 = _base()
+    per round, judged by the heat released after the deposit: the brackets
+    shrink as designed, and for each search the two members next to the
+    transition match the oracle's runs (heat release at the deposit end and
+    at the end, temperature peaks) at 1e-9 and take the oracle's outcome on
+    either side of it; without chemistry the highest energy does not
+    ignite."""
+    b0 = synth.ignition_base()
     b1 = with_energy(b0, b0.laser.E)
     b1.laser.sigma_t = 2.0 * b0.laser.sigma_t
     bases = [b0, b1]
     ctx = htr.Context.from_case(b0)
     E0 = b0.laser.E
-    nsteps, chunk, members = 40, 5, 4
+    n_after, chunk, members, kappa = 60, 5, 4, 1e-2
     dt = 0.5 * initial_stable_dt(ctx, b0)
-    # per search, a threshold halfway between the peaks of the lowest and highest energies
-    T_ign = []
-    for b in bases:
-        p_lo = _single_peak(with_energy(b, 0.25 * E0), nsteps, dt, chunk)
-        p_hi = _single_peak(with_energy(b, 2.0 * E0), nsteps, dt, chunk)
-        print(f"sigma_t {b.laser.sigma_t:.3e}: peak T {p_lo:.3f} K at 0.25 E0, {p_hi:.3f} K at 2 E0", flush=True)
-        assert p_hi > p_lo + 1.0
-        T_ign.append(0.5 * (p_lo + p_hi))
-    res = min_ignition_energies(ctx, bases, 0.25 * E0, 2.0 * E0, nsteps, T_ign, members=members, rounds=2,
+    res = min_ignition_energies(ctx, bases, 0.25 * E0, 2.0 * E0, n_after, kappa=kappa, members=members, rounds=2,
                                 chunk=chunk, dt=dt)
-    for i, (b, r) in enumerate(zip(bases, res)):
+    n_d = max(deposit_end_step(b.laser, dt) for b in bases)
+    for b, r in zip(bases, res):
         assert r.E_hi - r.E_lo == pytest.approx(1.75 * E0 / ((members - 1) * (members + 1)), rel=1e-9)
-        for energies, peaks, _ in r.rounds:
-            assert np.all(np.diff(peaks) > 0)
-        # batched peaks of the last round equal single-grid runs of the same members
-        energies, peaks, _ = r.rounds[-1]
-        for m in (0, members - 1):
-            assert peaks[m] == _single_peak(with_energy(b, energies[m]), nsteps, dt, chunk)
-        assert _single_peak(with_energy(b, r.E_lo), nsteps, dt, chunk) <= T_ign[i]
-        assert _single_peak(with_energy(b, r.E_hi), nsteps, dt, chunk) > T_ign[i]
+        assert 0.25 * E0 < r.E_lo < r.E_hi < 2.0 * E0
+        # the two members of the search next to the transition, against the oracle
+        ends = {}
+        for energies, runs, ig in r.rounds:
+            for m, E in enumerate(energies):
+                if E in (r.E_lo, r.E_hi):
+                    ends[E] = (runs, m, bool(ig[m]))
+        assert set(ends) == {r.E_lo, r.E_hi}
+        for E, (runs, m, ig) in ends.items():
+            J_d, J_end, J_last, peak, fin = _oracle_run(with_energy(b, E), n_d, n_after, dt, chunk)
+            print(f"sigma_t {b.laser.sigma_t:.3e} E/E0 {E / E0:.4f}: released/E {(J_end - J_d) / E:+.4e} "
+                  f"(GPU {runs.released()[m] / E:+.4e}), peak T {peak:.2f} K", flush=True)
+            assert runs.J_d[m] == pytest.approx(J_d, rel=1e-9, abs=1e-9 * abs(J_end))
+            assert runs.J_end[m] == pytest.approx(J_end, rel=1e-9)
+            assert runs.J_last[m] == pytest.approx(J_last, rel=1e-9)
+            assert runs.peak_T[m] == pytest.approx(peak, rel=1e-9)
+            assert runs.final_max_T[m] == pytest.approx(fin, rel=1e-9)
+            oracle_ig = (J_end - J_d >= kappa * E) and (J_end - J_last > 0.0)
+            assert ig == oracle_ig == (E == r.E_hi)
+    # the inert control: no chemistry, no heat release, no ignition
+    inert = htr.Context.from_case(b0, flags=synth.CHEM_OFF)
+    runs = run_members(inert, [with_energy(b0, 2.0 * E0)], n_d, n_after, dt, chunk)
+    assert runs.released()[0] == 0.0 and not ignited(runs, [2.0 * E0], kappa)[0]
