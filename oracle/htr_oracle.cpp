@@ -52,6 +52,8 @@ static const double PI = 3.14159265358979323846;
 
 enum { OK = 0, EINVAL = 1, ENONFINITE = 4, ENEWTON = 5, ETRANGE = 6 };
 enum { CHEM_OFF = 1u, VISC_OFF = 2u, FORCE_CENTRAL = 4u, FORCE_TENO = 8u, WENO3Z = 16u };
+// boundary types of a bounded axis side
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
 
 // ------------------------------------------------------------- dual numbers
 struct Dual {
@@ -103,6 +105,15 @@ struct Case {
   std::vector<double> mt[9];         // node metric terms (d xi_d / d x_c) / J at mt[3d + c]
   std::vector<double> mf[9];         // the same at face i+1/2 along d
   std::vector<double> Jac;           // J = det(d xi / d x) at nodes (1 / index-space cell volume)
+  // Non-periodic boundaries (Methods › Diffusion flame › Physical model and
+  // numerical setup; Methods › Model rocket combustor › Numerical setup):
+  // per axis and side (0: low, 1: high) a boundary type; an axis is either
+  // periodic on both sides or bounded on both.  On a bounded axis the first
+  // and last nodes lie on the boundaries.
+  int bc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  double pinf[3][2] = {{0, 0}, {0, 0}, {0, 0}};    // outflow: far-field pressure
+  double relax[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // outflow: relaxation coefficient sigma
+  bool bounded(int a) const { return bc[a][0] != 0; }
   long long N() const { return (long long)n[0] * n[1] * n[2]; }
   long long idx(int i, int j, int k) const { return ((long long)k * n[1] + j) * n[0] + i; }
 };
@@ -310,6 +321,10 @@ static void chemistry(const Case& C, const Params<S>& P, const S* Uc, Cell<S>& z
 template <class S>
 static S laser_axis(const Case& C, const Params<S>& P, int a, int i) {
   if (C.n[a] == 1) return S(1);
+  if (C.bounded(a)) {   // no periodic images across a boundary
+    S z = (C.xnode[a][i] - P.xc[a]) / P.sr;
+    return exp(-0.5 * z * z);
+  }
   double Lp = C.L[a];
   S r = C.xnode[a][i] - P.xc[a];
   double shift = Lp * std::nearbyint(val(r) / Lp);   // minimum image (a discrete choice)
@@ -542,6 +557,24 @@ template <class S> static S teno6(const S* f, double CT, double* detail = nullpt
 }
 
 // ----------------------------------------------------------------- the RHS
+// d phi / d x_a at node c of a rectilinear grid: the second-order central
+// difference, on a bounded axis one-sided second order at the boundary nodes
+// (-3, 4, -1)/2 inward.  get(q) returns phi at linear index q.
+template <class S, class Get>
+static S nodal_diff(const Case& C, int a, const int* c, Get get) {
+  const int n = C.n[a];
+  auto at = [&](int i) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[a] = C.bounded(a) ? i : wrap(i, n);
+    return get(C.idx(cc[0], cc[1], cc[2]));
+  };
+  const double xi = C.xin[a][c[a]];
+  const int i = c[a];
+  if (C.bounded(a) && i == 0) return xi * (-3.0 * at(0) + 4.0 * at(1) - at(2)) / 2.0;
+  if (C.bounded(a) && i == n - 1) return xi * (3.0 * at(n - 1) - 4.0 * at(n - 2) + at(n - 3)) / 2.0;
+  return xi * (at(i + 1) - at(i - 1)) / 2.0;
+}
+
 template <class S> struct Fields {
   std::vector<Cell<S>> cell;
   std::vector<double> theta;   // sensor per node
@@ -590,7 +623,8 @@ static int eval_cells(const Case& C, const Params<S>& P, const S* U, double* T_i
             g[b][m] += C.Jac[q] * C.mt[3 * a + b][q] * (val(zp.u[m]) - val(zm.u[m])) / 2.0;
         continue;
       }
-      for (int m = 0; m < 3; ++m) g[a][m] = C.xin[a][c[a]] * (val(zp.u[m]) - val(zm.u[m])) / 2.0;
+      for (int m = 0; m < 3; ++m)
+        g[a][m] = nodal_diff<double>(C, a, c, [&](long long qq) { return val(F.cell[qq].u[m]); });
     }
     double div = g[0][0] + g[1][1] + g[2][2];
     double wx = g[1][2] - g[2][1], wy = g[2][0] - g[0][2], wz = g[0][1] - g[1][0];
@@ -662,6 +696,59 @@ static int conv_flux(const Case& C, const S* U, const Fields<S>& F, int d, const
   return 1;
 }
 
+// Step 3b near a boundary of a bounded axis, where the six-point stencil
+// does not fit: the face i+1/2 between nodes st[k-1] and st[k] (k = m/2) of
+// an m-point stencil (m = 4: nodes i-1..i+2; m = 2: nodes i, i+1).  Central
+// faces take the widest centred interpolation that fits, (-1, 7, 7, -1)/12
+// or (1, 1)/2; faces the hybrid switch marks (sensor over the m nodes, or
+// the pressure jump) take the first-order local Lax-Friedrichs (Rusanov)
+// flux of the two face nodes, alpha = max over the m nodes of |u_n| + c.
+template <class S>
+static int conv_flux_reduced(const Case& C, const S* U, const Fields<S>& F, int d, const long long* st, int m,
+                             S* out) {
+  const long long N = C.N();
+  const int nv = C.ns + 4;
+  const int a = m / 2 - 1, b = m / 2;   // the face's two nodes within st
+  bool flag;
+  if (C.flags & FORCE_TENO) flag = true;
+  else if (C.flags & FORCE_CENTRAL) flag = false;
+  else {
+    double th = 0;
+    for (int k = 0; k < m; ++k) th = std::max(th, F.theta[st[k]]);
+    double pa = val(F.cell[st[a]].p), pb = val(F.cell[st[b]].p);
+    double psi = std::fabs(pb - pa) / std::min(pa, pb);
+    flag = (th > C.theta_c) || (psi > C.psi_c);
+  }
+  std::vector<S> Uk(nv * m);
+  for (int k = 0; k < m; ++k)
+    for (int v = 0; v < nv; ++v) Uk[k * nv + v] = U[v * N + st[k]];
+  if (!flag) {
+    for (int v = 0; v < nv; ++v) {
+      if (m == 4) {
+        S s = -node_flux(C, &Uk[0], F.cell[st[0]], v, d) + 7.0 * node_flux(C, &Uk[nv], F.cell[st[1]], v, d) +
+              7.0 * node_flux(C, &Uk[2 * nv], F.cell[st[2]], v, d) - node_flux(C, &Uk[3 * nv], F.cell[st[3]], v, d);
+        out[v] = s / 12.0;
+      } else {
+        out[v] = (node_flux(C, &Uk[0], F.cell[st[0]], v, d) + node_flux(C, &Uk[nv], F.cell[st[1]], v, d)) / 2.0;
+      }
+    }
+    return 0;
+  }
+  int am = 0;
+  double best = -1;
+  for (int k = 0; k < m; ++k) {
+    double sp = std::fabs(val(F.cell[st[k]].u[d])) + val(F.cell[st[k]].c);
+    if (sp > best) { best = sp; am = k; }
+  }
+  S alpha = fabs(F.cell[st[am]].u[d]) + F.cell[st[am]].c;
+  for (int v = 0; v < nv; ++v) {
+    S fa = node_flux(C, &Uk[a * nv], F.cell[st[a]], v, d);
+    S fb = node_flux(C, &Uk[b * nv], F.cell[st[b]], v, d);
+    out[v] = (fa + fb) / 2.0 - alpha * (Uk[b * nv + v] - Uk[a * nv + v]) / 2.0;
+  }
+  return 1;
+}
+
 // Step 3c: diffusive flux at face i+1/2 along d (eqs. 1-3, 5, 6), sign as it
 // enters the right-hand side.  A second-order compact face form: normal
 // derivatives from the two adjacent nodes, tangential derivatives as the mean
@@ -683,12 +770,8 @@ static void diff_flux(const Case& C, const Fields<S>& F, int d, int i, int j, in
     if (a == d || C.n[a] == 1) continue;
     for (int side = 0; side < 2; ++side) {
       const int* c = side ? c1 : c0;
-      int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
-      cp[a] = wrap(c[a] + 1, C.n[a]);
-      cm[a] = wrap(c[a] - 1, C.n[a]);
-      const Cell<S>& zp = F.cell[C.idx(cp[0], cp[1], cp[2])];
-      const Cell<S>& zm = F.cell[C.idx(cm[0], cm[1], cm[2])];
-      for (int m = 0; m < 3; ++m) grad[a][m] += 0.5 * C.xin[a][c[a]] * (zp.u[m] - zm.u[m]) / 2.0;
+      for (int m = 0; m < 3; ++m)
+        grad[a][m] += 0.5 * nodal_diff<S>(C, a, c, [&](long long qq) { return F.cell[qq].u[m]; });
     }
   }
   S mu = 0.5 * (A.mu + B.mu), lam = 0.5 * (A.lam + B.lam), rho = 0.5 * (A.rho + B.rho);
@@ -870,6 +953,132 @@ static void diff_flux_curv(const Case& C, const Fields<S>& F, int d, int i, int 
   out[ns + 3] = work - qn;
 }
 
+// Step 5, boundary nodes of bounded axes (Poinsot & Lele's characteristic
+// boundary conditions, cited by the paper as NSCBC).  The normal convective
+// terms at a boundary node are written as the locally one-dimensional wave
+// amplitudes along the axis (one-sided derivatives at the node, u_n the
+// velocity along the axis, c the frozen sound speed):
+//   L1 = (u_n - c)(dp - rho c du_n),  L5 = (u_n + c)(dp + rho c du_n),
+//   L2 = u_n (c^2 drho - dp),  L3, L4 = u_n du_t,  LY_s = u_n dY_s,
+// whose primitive rates are
+//   rho_t = -(L2 + (L5 + L1)/2) / c^2,  p_t = -(L5 + L1)/2,
+//   un_t = -(L5 - L1)/(2 rho c),  ut_t = -L3, -L4,  Y_t = -LY.
+// Waves entering the domain are replaced:
+// - outflow: the entering acoustic wave relaxes p to p_inf,
+//   L = K (p - p_inf) with K = sigma c (1 - M^2) / L_axis; entering
+//   entropy, shear and species waves (backflow) are zero; the normal
+//   gradients of the diffusive fluxes are taken as zero;
+// - wall (no-slip, isothermal) and inflow (velocity, temperature and, for
+//   the inflow, composition imposed): these are held at the node's values
+//   and the entering acoustic wave equals the leaving one.  At a wall
+//   (u_n = 0) there is no entropy wave, L2 = 0, so rho_t = -L_out / c^2 (the
+//   continuity equation; the held T stands for the heat the wall takes); at
+//   an inflow the entropy wave holds T, L2 = (gamma - 1)(L5 + L1)/2, so
+//   rho_t = -(gamma / c^2) L_out.  At a wall the species diffuse with zero
+//   flux through the wall (half control volume); momentum and energy follow
+//   from the held u and T.
+// Tangential fluxes and sources at the node are those of any other node.
+template <class S>
+static void boundary_nodes(const Case& C, const Fields<S>& F, const std::vector<S>* Fd, S* dUdt) {
+  const long long N = C.N();
+  const int ns = C.ns, nv = ns + 4;
+#pragma omp parallel for schedule(static)
+  for (long long q = 0; q < N; ++q) {
+    int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+    bool onb = false;
+    for (int a = 0; a < 3; ++a)
+      if (C.bounded(a) && (c[a] == 0 || c[a] == C.n[a] - 1)) onb = true;
+    if (!onb) continue;
+    const Cell<S>& z = F.cell[q];
+    const S cv = z.cp - Ru / z.W, gam = z.cp / cv, cc = z.c, cc2 = z.c * z.c;
+    bool held = false, holdY = false;
+    std::vector<S> add(nv, S(0));   // outflow sides: conserved rates; held sides: species terms
+    for (int a = 0; a < 3; ++a) {
+      if (!C.bounded(a)) continue;
+      for (int side = 0; side < 2; ++side) {
+        if (c[a] != (side ? C.n[a] - 1 : 0)) continue;
+        const int type = C.bc[a][side];
+        const double sgn = side ? 1.0 : -1.0;   // outward normal along a
+        auto D = [&](auto get) { return nodal_diff<S>(C, a, c, get); };
+        S Dp = D([&](long long qq) { return F.cell[qq].p; });
+        S Dr = D([&](long long qq) { return F.cell[qq].rho; });
+        S Du[3];
+        for (int m = 0; m < 3; ++m) Du[m] = D([&](long long qq) { return F.cell[qq].u[m]; });
+        const S un = z.u[a];
+        S L1 = (un - cc) * (Dp - z.rho * cc * Du[a]);
+        S L5 = (un + cc) * (Dp + z.rho * cc * Du[a]);
+        if (type == BC_WALL || type == BC_INFLOW) {
+          held = true;
+          if (type == BC_INFLOW) holdY = true;
+          // the entering acoustic wave equals the leaving one; at a wall
+          // u_n = 0 carries no entropy wave, at an inflow the entropy wave
+          // holds T: L2 = (gamma - 1)(L5 + L1)/2
+          const S Lout = side ? L5 : L1;
+          const S drho = (type == BC_INFLOW ? -(gam / cc2) : -(1.0 / cc2)) * Lout;
+          for (int s = 0; s < ns; ++s) add[s] += z.Y[s] * drho;
+          if (type == BC_WALL && !(C.flags & VISC_OFF)) {
+            // zero species flux through the wall: half control volume at the node
+            const long long qf = side ? q - (long long)(a == 0 ? 1 : (a == 1 ? C.n[0] : C.n[0] * C.n[1])) : q;
+            const double x2 = 2.0 * C.xin[a][c[a]];
+            for (int s = 0; s < ns; ++s) add[s] += (side ? -x2 : x2) * Fd[a][(size_t)qf * nv + s];
+          }
+          continue;
+        }
+        // outflow
+        S L2 = un * (cc2 * Dr - Dp);
+        S L3 = un * Du[(a + 1) % 3], L4 = un * Du[(a + 2) % 3];
+        std::vector<S> LY(ns);
+        for (int s = 0; s < ns; ++s) LY[s] = un * D([&](long long qq) { return F.cell[qq].Y[s]; });
+        const double Ld = std::fabs(C.xnode[a][C.n[a] - 1] - C.xnode[a][0]);
+        const S M = fabs(un) / cc;
+        const S K = C.relax[a][side] * cc * (1.0 - M * M) / Ld;
+        const S relaxp = K * (z.p - C.pinf[a][side]);
+        if (sgn * val(un - cc) < 0) L1 = relaxp;
+        if (sgn * val(un + cc) < 0) L5 = relaxp;
+        if (sgn * val(un) < 0) {
+          L2 = 0; L3 = 0; L4 = 0;
+          for (int s = 0; s < ns; ++s) LY[s] = 0;
+        }
+        const S rho_t = -(L2 + 0.5 * (L5 + L1)) / cc2;
+        const S p_t = -0.5 * (L5 + L1);
+        S u_t[3];
+        u_t[a] = -(L5 - L1) / (2.0 * z.rho * cc);
+        u_t[(a + 1) % 3] = -L3;
+        u_t[(a + 2) % 3] = -L4;
+        S ke = 0, udu = 0;
+        for (int m = 0; m < 3; ++m) { ke += z.u[m] * z.u[m]; udu += z.u[m] * u_t[m]; }
+        S dE = (z.cp * z.W / Ru - 1.0) * p_t + 0.5 * ke * rho_t + z.rho * udu;
+        for (int s = 0; s < ns; ++s) {
+          S drs = z.Y[s] * rho_t - z.rho * LY[s];
+          add[s] += drs;
+          dE += (z.h[s] - z.cp * z.T * z.W / C.W[s]) * drs;
+        }
+        for (int m = 0; m < 3; ++m) add[ns + m] += z.u[m] * rho_t + z.rho * u_t[m];
+        add[ns + 3] += dE;
+      }
+    }
+    if (!held) {
+      for (int v = 0; v < nv; ++v) dUdt[v * N + q] += add[v];
+      continue;
+    }
+    // held node: species rates from every term, then u and T (and Y) held
+    std::vector<S> drs(ns);
+    S drho = 0;
+    for (int s = 0; s < ns; ++s) { drs[s] = dUdt[s * N + q] + add[s]; drho += drs[s]; }
+    if (holdY)
+      for (int s = 0; s < ns; ++s) drs[s] = z.Y[s] * drho;
+    S ke = 0;
+    for (int m = 0; m < 3; ++m) ke += z.u[m] * z.u[m];
+    S dE = 0;
+    for (int s = 0; s < ns; ++s) {
+      dUdt[s * N + q] = drs[s];
+      dE += (z.h[s] - Ru * z.T / C.W[s] + 0.5 * ke) * drs[s];
+    }
+    for (int m = 0; m < 3; ++m) dUdt[(ns + m) * N + q] = z.u[m] * drho;
+    dUdt[(ns + 3) * N + q] = dE;
+  }
+}
+
 template <class S>
 static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, double t, S* dUdt,
                S* hrr_out, unsigned char* mask, Fields<S>* keep) {
@@ -887,21 +1096,38 @@ static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, doub
     dUdt[(ns + 3) * N + q] = F.cell[q].qL;
     if (hrr_out) hrr_out[q] = F.cell[q].hrr;
   }
+  std::vector<S> FdKeep[3];
+  bool anyb = false;
   for (int d = 0; d < 3; ++d) {
     if (C.n[d] == 1) continue;
-    // face fluxes, face f = i+1/2 stored at the index of node i
+    const bool bnd = C.bounded(d);
+    anyb = anyb || bnd;
+    const int n = C.n[d];
+    // face fluxes, face f = i+1/2 stored at the index of node i (on a bounded
+    // axis faces i = 0 .. n-2 only)
     std::vector<S> Fc((size_t)N * nv), Fd((size_t)N * nv);
 #pragma omp parallel for schedule(static)
     for (long long q = 0; q < N; ++q) {
       int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+      if (bnd && c[d] == n - 1) {
+        if (mask) mask[(size_t)d * N + q] = 0;
+        continue;
+      }
+      // stencil: six points i-2..i+3, or near a boundary the reduced m points
+      int m = 6, start = c[d] - 2;
+      if (bnd && (c[d] < 2 || c[d] > n - 4)) {
+        m = (c[d] == 0 || c[d] == n - 2) ? 2 : 4;
+        start = c[d] - m / 2 + 1;
+      }
       long long st[6];
-      for (int m = 0; m < 6; ++m) {
+      for (int k = 0; k < m; ++k) {
         int cc[3] = {c[0], c[1], c[2]};
-        cc[d] = wrap(c[d] - 2 + m, C.n[d]);
-        st[m] = C.idx(cc[0], cc[1], cc[2]);
+        cc[d] = bnd ? start + k : wrap(start + k, n);
+        st[k] = C.idx(cc[0], cc[1], cc[2]);
       }
       std::vector<S> fc(nv), fd(nv);
-      int te = C.curv ? conv_flux_curv(C, U, F, d, q, st, fc.data()) : conv_flux(C, U, F, d, st, fc.data());
+      int te = C.curv ? conv_flux_curv(C, U, F, d, q, st, fc.data())
+                      : (m == 6 ? conv_flux(C, U, F, d, st, fc.data()) : conv_flux_reduced(C, U, F, d, st, m, fc.data()));
       if (mask) mask[(size_t)d * N + q] = (unsigned char)te;
       if (C.flags & VISC_OFF) for (int v = 0; v < nv; ++v) fd[v] = 0;
       else if (C.curv) diff_flux_curv(C, F, d, c[0], c[1], c[2], fd.data());
@@ -909,11 +1135,13 @@ static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, doub
       for (int v = 0; v < nv; ++v) { Fc[(size_t)q * nv + v] = fc[v]; Fd[(size_t)q * nv + v] = fd[v]; }
     }
     // flux differences: dU/dt += xi_d (-(Fc_{i+1/2} - Fc_{i-1/2}) + (Fd_{i+1/2} - Fd_{i-1/2})),
-    // on a curvilinear grid J times the mapped flux difference (index spacing 1)
+    // on a curvilinear grid J times the mapped flux difference (index spacing 1);
+    // on a bounded axis at the interior nodes only
     for (long long q = 0; q < N; ++q) {
       int c[3] = {(int)(q % C.n[0]), (int)((q / C.n[0]) % C.n[1]), (int)(q / ((long long)C.n[0] * C.n[1]))};
+      if (bnd && (c[d] == 0 || c[d] == n - 1)) continue;
       int cm[3] = {c[0], c[1], c[2]};
-      cm[d] = wrap(c[d] - 1, C.n[d]);
+      cm[d] = wrap(c[d] - 1, n);
       long long qm = C.idx(cm[0], cm[1], cm[2]);
       double xi = C.curv ? C.Jac[q] : C.xin[d][c[d]];
       for (int v = 0; v < nv; ++v) {
@@ -922,7 +1150,9 @@ static int rhs(const Case& C, const Params<S>& P, const S* U, double* T_io, doub
         dUdt[v * N + q] += xi * (dif - conv);
       }
     }
+    if (bnd) FdKeep[d] = std::move(Fd);
   }
+  if (anyb) boundary_nodes(C, F, FdKeep, dUdt);
   return OK;
 }
 
@@ -1040,6 +1270,29 @@ void* orc_case_new(int ns, int nr, const double* W, const double* a7, const doub
 
 void orc_case_free(void* h) { delete (Case*)h; }
 
+// Boundary conditions: bc[3][2] per axis and side (0 periodic, 1 no-slip
+// isothermal wall, 2 inflow, 3 outflow; an axis periodic on both sides or
+// bounded on both), pinf[3][2] and relax[3][2] the outflow's far-field
+// pressure and relaxation coefficient.  A bounded axis needs at least 8
+// nodes; curvilinear grids stay periodic.  Returns 1 (EINVAL) otherwise.
+int orc_case_set_boundaries(void* h, const int* bc, const double* pinf, const double* relax) {
+  Case& C = *(Case*)h;
+  if (C.curv) return EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = bc[2 * a], hi = bc[2 * a + 1];
+    if ((lo == BC_PERIODIC) != (hi == BC_PERIODIC)) return EINVAL;
+    if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return EINVAL;
+    if (lo != BC_PERIODIC && C.n[a] < 8) return EINVAL;
+    for (int side = 0; side < 2; ++side) {
+      if (bc[2 * a + side] == BC_OUTFLOW && !(pinf[2 * a + side] > 0 && relax[2 * a + side] >= 0)) return EINVAL;
+      C.bc[a][side] = bc[2 * a + side];
+      C.pinf[a][side] = pinf[2 * a + side];
+      C.relax[a][side] = relax[2 * a + side];
+    }
+  }
+  return OK;
+}
+
 // Makes the case curvilinear: node coordinates xyz[3][N] and lattice periods
 // P[3][3] (row a: the displacement along index a over n[a] cells).  An
 // inactive axis must have its period along its own coordinate axis, and the
@@ -1047,6 +1300,8 @@ void orc_case_free(void* h) { delete (Case*)h; }
 // a node with det(d x / d xi) <= 0.
 int orc_case_set_curvilinear(void* h, const double* xyz, const double* P) {
   Case& C = *(Case*)h;
+  for (int a = 0; a < 3; ++a)
+    if (C.bounded(a)) return EINVAL;
   const long long N = C.N();
   for (int c = 0; c < 3; ++c) C.X[c].assign(xyz + c * N, xyz + (c + 1) * N);
   for (int a = 0; a < 3; ++a)

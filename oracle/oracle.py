@@ -50,6 +50,7 @@ def _bind(path):
                                C.c_double, C.c_uint]
     L.orc_case_free.argtypes = [C.c_void_p]
     L.orc_case_set_curvilinear.argtypes = [C.c_void_p, _dp, _dp]
+    L.orc_case_set_boundaries.argtypes = [C.c_void_p, _ip, _dp, _dp]
     L.orc_metrics.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.orc_set_flags.argtypes = [C.c_void_p, C.c_uint]
     L.orc_prim_to_cons.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
@@ -167,6 +168,11 @@ class Oracle:
         if self.curv:
             _chk(L.orc_case_set_curvilinear(self.h, f64(np.asarray(g.xyz).reshape(-1)),
                                             f64(np.asarray(g.period).reshape(-1))))
+        bc = np.ascontiguousarray(np.asarray(getattr(case, "bc", ((0, 0),) * 3), dtype=np.int32).reshape(-1))
+        if bc.any():
+            self._keep.append(bc)
+            _chk(L.orc_case_set_boundaries(self.h, bc, f64(np.asarray(case.pinf, float).reshape(-1)),
+                                           f64(np.asarray(case.relax, float).reshape(-1))))
         self.case = case
 
     def __del__(self):
