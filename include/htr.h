@@ -71,6 +71,12 @@ typedef enum {
 #define HTR_WENO3Z       16u   /* WENO3-Z instead of TENO6 where the scheme captures shocks
                                   (Methods › Numerical method's alternative; no adjoint: HTR_EUNSUPPORTED)    */
 
+/* boundary types of a non-periodic axis side (htr_set_boundaries) */
+#define HTR_BC_PERIODIC 0
+#define HTR_BC_WALL     1      /* no-slip, isothermal: u and T held at the node's values */
+#define HTR_BC_INFLOW   2      /* velocity, temperature and composition held             */
+#define HTR_BC_OUTFLOW  3      /* characteristic outflow relaxing p to p_inf             */
+
 typedef struct htr_ctx htr_ctx;
 typedef struct htr_batch htr_batch;
 
@@ -176,6 +182,35 @@ htr_status htr_grid_metrics(htr_ctx* ctx, double* mt, double* mf, void* stream);
  * tracked: the caller synchronises its graph launches first.  NULL is
  * HTR_EINVAL. */
 htr_status htr_destroy(htr_ctx* ctx);
+/* Non-periodic boundaries of a rectilinear single-grid context (Methods ›
+ * Diffusion flame › Physical model and numerical setup: characteristic
+ * in/outflow boundaries after Poinsot & Lele and no-slip walls; Methods ›
+ * Model rocket combustor › Numerical setup: isothermal walls).
+ *   bc[a][side]     HOST, per axis a and side (0 low, 1 high): HTR_BC_*; an
+ *                   axis is periodic on both sides or bounded on both
+ *   pinf[a][side]   HOST, far-field pressure of an outflow side (Pa, > 0)
+ *   relax[a][side]  HOST, relaxation coefficient sigma of an outflow side
+ *                   (>= 0; K = sigma c (1 - M^2) / L_axis)
+ * On a bounded axis the first and last nodes lie on the boundary (their
+ * xnode are the boundary positions).  Faces whose six-point stencil does not
+ * fit take the widest centred interpolation that does, or the local
+ * Lax-Friedrichs (Rusanov) flux where the hybrid switch marks them; the
+ * sensor and tangential derivatives are one-sided at boundary nodes.
+ * Boundary nodes take the locally one-dimensional characteristic treatment:
+ * an outflow's entering acoustic wave relaxes p to p_inf (entering entropy,
+ * shear and species waves of a backflow are zero; zero normal gradient of
+ * the diffusive fluxes); walls hold the node's velocity and temperature
+ * (set them to the wall's in the state), its density following continuity
+ * and its species diffusing with zero flux through the wall; inflows hold
+ * velocity, temperature and composition.  A bounded axis needs n >= 8; the
+ * laser sums no images across it.  Errors (before any device work):
+ * HTR_EINVAL for NULL, mismatched sides, n < 8, bad types or outflow
+ * parameters; HTR_EUNSUPPORTED on a curvilinear context.  Ensembles built
+ * from the context, the tape and the adjoint calls return HTR_EUNSUPPORTED
+ * once any axis is bounded.  All-periodic bc restores the periodic grid. */
+htr_status htr_set_boundaries(htr_ctx* ctx, const int32_t bc[3][2], const double pinf[3][2],
+                              const double relax[3][2]);
+
 /* Replace the scheme flags of an existing context. */
 htr_status htr_set_flags(htr_ctx* ctx, uint32_t flags);
 /* Number of cells of the context's grid (0 for NULL). */

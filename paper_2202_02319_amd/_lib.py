@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "HTR_OK", 1: "HTR_EINVAL", 2: "HTR_ENOMEM", 3: "HTR_EDEVICE",
                 5: "HTR_ENEWTON", 6: "HTR_ETRANGE", 7: "HTR_EUNSUPPORTED"}
 HTR_MAX_NS, HTR_MAX_NR, HTR_MAX_SIDE = 12, 64, 3
 HTR_CHEM_OFF, HTR_VISC_OFF, HTR_FORCE_CENTRAL, HTR_FORCE_TENO, HTR_WENO3Z = 1, 2, 4, 8, 16
+HTR_BC_PERIODIC, HTR_BC_WALL, HTR_BC_INFLOW, HTR_BC_OUTFLOW = 0, 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -74,6 +75,7 @@ def load():
         "htr_grid_metrics": (st, [vp, vp, vp, vp]),
         "htr_destroy": (st, [vp]),
         "htr_set_flags": (st, [vp, C.c_uint32]),
+        "htr_set_boundaries": (st, [vp, vp, vp, vp]),
         "htr_num_cells": (C.c_int64, [vp]),
         "htr_prim_to_cons": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "htr_rhs": (st, [vp, vp, vp, C.c_double, C.POINTER(htr_laser), vp, vp, vp]),

@@ -93,6 +93,7 @@ htr_status htr_rhs_adjoint(htr_ctx* c, const double* U, double* T_io, double t, 
   if (c->scheme.flags & HTR_WENO3Z)
     return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for rectilinear grids");
+  if (c->host_mem.bounded) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for periodic grids");
   if (!U || !T_io || !lam || !Ubar_acc || !pbar_acc || !adj_work) return fail(HTR_EINVAL, "NULL pointer");
   if (Ubar_acc == lam || Ubar_acc == U) return fail(HTR_EINVAL, "Ubar_acc must not alias U or lam");
   if (!std::isfinite(t) || !std::isfinite(s) || !std::isfinite(h)) return fail(HTR_EINVAL, "t, s, h must be finite");
@@ -111,6 +112,7 @@ htr_status htr_rk3_step_adjoint(htr_ctx* c, const double* Un, const double* stag
   if (c->scheme.flags & HTR_WENO3Z)
     return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for the TENO6 scheme (HTR_WENO3Z is set)");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for rectilinear grids");
+  if (c->host_mem.bounded) return fail(HTR_EUNSUPPORTED, "the discrete adjoint is built for periodic grids");
   if (!Un || !stages || !T_io || !Ubar || !pbar_acc || !adj_work) return fail(HTR_EINVAL, "NULL pointer");
   if (!std::isfinite(t) || !(dt > 0) || !std::isfinite(Jbar)) return fail(HTR_EINVAL, "need finite t, Jbar and dt > 0");
   htr_status st = check_laser(laser);

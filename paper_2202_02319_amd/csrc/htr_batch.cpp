@@ -45,6 +45,7 @@ htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* m
   *out = nullptr;
   if (!ctx || !mds) return fail(HTR_EINVAL, "ctx or members is NULL");
   if (nmem < 1) return fail(HTR_EINVAL, "nmem must be >= 1");
+  if (ctx->host_mem.bounded) return fail(HTR_EUNSUPPORTED, "ensembles are built on periodic grids");
   const int nr = ctx->nr;
   htr_batch* b = new htr_batch();
   b->ctx = ctx;

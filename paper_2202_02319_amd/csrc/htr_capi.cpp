@@ -308,6 +308,13 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
                        C.scheme.psi_c,
                        C.scheme.teno_CT, s));
   }
+  if (C.bounded) {
+    // the cells next to non-periodic boundaries: their whole right-hand side
+    if (teno_bits) return fail(HTR_EUNSUPPORTED, "no tape on a grid with non-periodic boundaries");
+    TimedLaunch tl(C.timer, TC_UPDATE, s);
+    HIP_OK(launch_bnd(C.ns, C.M, C.mem, C.nblocks, a, U, T, w.aux, w.src, w.flag, w.grad, w.part, C.scheme.psi_c,
+                      C.scheme.teno_CT, s));
+  }
   {
     TimedLaunch tl(C.timer, TC_DIFF, s);
     HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, Un, T, w.aux, w.grad, w.part, out, ca,
@@ -373,6 +380,7 @@ Ctx htr::view(const htr_ctx* c) {
     v.L1[a] = c->L[a];
   }
   v.timer = const_cast<Timer*>(&c->timer);
+  v.bounded = c->host_mem.bounded != 0;
   if (c->curv) {
     const long long N = c->N;
     v.curv = &c->cg;
@@ -602,6 +610,34 @@ htr_status htr_destroy(htr_ctx* c) {
   return HTR_OK;
 }
 
+htr_status htr_set_boundaries(htr_ctx* c, const int32_t bc[3][2], const double pinf[3][2],
+                              const double relax[3][2]) {
+  if (!c || !bc || !pinf || !relax) return fail(HTR_EINVAL, "NULL argument");
+  if (c->curv) return fail(HTR_EUNSUPPORTED, "non-periodic boundaries are for rectilinear grids");
+  Member M = c->host_mem;
+  M.bounded = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = bc[a][0], hi = bc[a][1];
+    if (lo < HTR_BC_PERIODIC || lo > HTR_BC_OUTFLOW || hi < HTR_BC_PERIODIC || hi > HTR_BC_OUTFLOW)
+      return fail(HTR_EINVAL, "axis %d: unknown boundary type", a);
+    if ((lo == HTR_BC_PERIODIC) != (hi == HTR_BC_PERIODIC))
+      return fail(HTR_EINVAL, "axis %d: periodic on one side only", a);
+    if (lo != HTR_BC_PERIODIC && c->n[a] < 8) return fail(HTR_EINVAL, "axis %d: a bounded axis needs n >= 8", a);
+    for (int side = 0; side < 2; ++side) {
+      if (bc[a][side] == HTR_BC_OUTFLOW && !(pinf[a][side] > 0 && relax[a][side] >= 0 && std::isfinite(relax[a][side])))
+        return fail(HTR_EINVAL, "axis %d side %d: outflow needs p_inf > 0 and relax >= 0", a, side);
+      M.bc[a][side] = bc[a][side];
+      M.pinf[a][side] = pinf[a][side];
+      M.relax[a][side] = relax[a][side];
+    }
+    if (lo != HTR_BC_PERIODIC) M.bounded = 1;
+  }
+  Marked mk_(&c->fence, nullptr);
+  HIP_OK(hipMemcpy(c->dmem, &M, sizeof(Member), hipMemcpyHostToDevice));
+  c->host_mem = M;
+  return HTR_OK;
+}
+
 htr_status htr_set_flags(htr_ctx* c, uint32_t flags) {
   if (!c) return fail(HTR_EINVAL, "ctx is NULL");
   if ((flags & HTR_FORCE_CENTRAL) && (flags & HTR_FORCE_TENO))
@@ -705,6 +741,7 @@ htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev
   if (!U || !T_io || !t_dev || !dt_dev || !work || !tape) return fail(HTR_EINVAL, "NULL pointer");
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for rectilinear grids");
+  if (c->host_mem.bounded) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for periodic grids");
   htr_status st = check_laser(laser);
   if (st) return st;
   Ctx C = view(c);

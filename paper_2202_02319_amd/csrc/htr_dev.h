@@ -75,7 +75,24 @@ struct Member {
   double L[3];
   LaserDev laser;
   const double* dlnA;         // nullable [nr]
+  // non-periodic boundaries of a single-grid context (htr_set_boundaries):
+  // per axis and side the boundary type (HTR_BC_*; 0 periodic), the
+  // outflow's far-field pressure and relaxation coefficient
+  int bc[3][2];
+  double pinf[3][2];
+  double relax[3][2];
+  int bounded;                // any axis bounded
 };
+
+// Whether cell coordinate c lies within three nodes of a bounded boundary:
+// the cells whose right-hand side the boundary kernel writes.
+__device__ __forceinline__ bool in_boundary_slab(const Member& G, const int c[3]) {
+  if (!G.bounded) return false;
+  bool s = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s = s || (G.bc[a][0] != 0 && (c[a] < 3 || c[a] > G.n[a] - 4));
+  return s;
+}
 
 // General curvilinear grid of a single-grid context (Methods › Numerical method, the mapped
 // equations): metric terms at nodes and faces, node coordinates, lattice.
@@ -186,6 +203,11 @@ hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem,
                        const CallArgs& a,
                        const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
                        unsigned char* bits, double psi_c, double CT, hipStream_t s);
+// Right-hand side of the cells next to non-periodic boundaries (single
+// grid), written over the convective sweep's part[] for those cells.
+hipError_t launch_bnd(int ns, const MechTables* M, const Member* mem, int nblocks, const CallArgs& a, const double* U,
+                      const double* T, const double* aux, const double* src, const unsigned char* flag,
+                      const double* grad, double* part, double psi_c, double CT, hipStream_t s);
 hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a,
                        const double* U, const double* Un, const double* T, const double* aux, const double* grad,

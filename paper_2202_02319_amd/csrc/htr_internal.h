@@ -91,6 +91,7 @@ struct Ctx {
   int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
   double L1[3] = {1, 1, 1};
   Timer* timer = nullptr;
+  bool bounded = false;           // single grid with non-periodic boundaries (boundary kernel)
   // curvilinear single grid (null: rectilinear sweeps)
   const CurvGeom* curv = nullptr;
   const Member* host1 = nullptr;  // host copy of the single member (curvilinear launch shapes)

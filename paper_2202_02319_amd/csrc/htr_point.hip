@@ -43,6 +43,10 @@ __device__ __forceinline__ double om11(double x, double Ts) {
 
 __device__ __forceinline__ double laser_axis(const LaserDev& L, const Member& G, int a, int i) {
   if (!G.act[a]) return 1.0;
+  if (G.bc[a][0] != 0) {   // bounded axis: no periodic images
+    const double z = (G.xnode[a][i] - L.xc[a]) / L.sr;
+    return exp(-0.5 * z * z);
+  }
   const double Lp = G.L[a];
   double r = G.xnode[a][i] - L.xc[a];
   r -= Lp * rint(r / Lp);
@@ -465,9 +469,19 @@ __device__ __forceinline__ void sensor_block(int bl, const Member* __restrict__ 
 #pragma unroll
     for (int mm = 0; mm < 3; ++mm) g[a][mm] = 0.0;
     if (!G.act[a]) continue;
+    const double xi = G.xin[a][c[a]];
+    if (G.bc[a][0] != 0 && (c[a] == 0 || c[a] == G.n[a] - 1)) {
+      // boundary node of a bounded axis: one-sided second order, inward
+      const long long s1 = c[a] == 0 ? stride[a] : -stride[a];
+#pragma unroll
+      for (int mm = 0; mm < 3; ++mm) {
+        const double v0 = vel[mm * N + q], v1 = vel[mm * N + q + s1], v2 = vel[mm * N + q + 2 * s1];
+        g[a][mm] = c[a] == 0 ? xi * (-3.0 * v0 + 4.0 * v1 - v2) / 2.0 : xi * (3.0 * v0 - 4.0 * v1 + v2) / 2.0;
+      }
+      continue;
+    }
     const long long qp = q + (wrapi(c[a] + 1, G.n[a]) - c[a]) * stride[a];
     const long long qm = q + (wrapi(c[a] - 1, G.n[a]) - c[a]) * stride[a];
-    const double xi = G.xin[a][c[a]];
 #pragma unroll
     for (int mm = 0; mm < 3; ++mm) g[a][mm] = xi * (vel[mm * N + qp] - vel[mm * N + qm]) / 2.0;
   }

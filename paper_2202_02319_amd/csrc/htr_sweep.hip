@@ -569,6 +569,12 @@ __device__ __forceinline__ void diff_tile(int bl, const MechTables* __restrict__
     if (G.act[2]) diff_dir<NS, 2>(M, G, o, l, gc, valid, N, U, T, aux, grad, s_Fd, acc);
   }
   if (!valid) return;
+  // next to a non-periodic boundary part[] holds the whole right-hand side
+  // (the boundary kernel's): no diffusive term is added here
+  if (in_boundary_slab(G, gc)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  }
   // every load before the first store: out may be the same array as U^n, so
   // the compiler could not otherwise move a later variable's loads above an
   // earlier variable's store, and each variable would cost a memory round trip
@@ -612,6 +618,285 @@ __global__ __launch_bounds__(BLKF, 3) void k_diff(const MechTables* __restrict__
     diff_tile<NS>(bl, M, mem, nmem, A, Ub, Unb, Tb, auxb, gradb, partb, outb, ca, cb, rhs_only);
     __syncthreads();   // the next tile reuses the LDS
   }
+}
+
+// ----------------------------------------------------- non-periodic boundaries
+// Cells within three nodes of a bounded boundary (in_boundary_slab) get
+// their whole right-hand side here, one thread per cell, evaluating each of
+// their faces on its own (the tiled sweeps assume periodic wrap).  On a
+// bounded axis the first and last nodes lie on the boundary; a face whose
+// six-point stencil does not fit takes the widest centred interpolation that
+// does ((-1, 7, 7, -1)/12 or (1, 1)/2), or, where the hybrid switch marks
+// it, the local Lax-Friedrichs (Rusanov) flux of its two nodes.  Boundary
+// nodes take the locally one-dimensional characteristic treatment of
+// Poinsot & Lele (the paper's NSCBC, Methods › Diffusion flame › Physical
+// model and numerical setup): the normal convective terms as wave
+// amplitudes from one-sided differences, entering waves prescribed
+// (outflow: the acoustic one relaxes p to p_inf; walls and inflows hold u
+// and T, inflows also Y, with the entering acoustic wave equal to the
+// leaving one; Methods › Model rocket combustor › Numerical setup).
+
+__device__ __forceinline__ double cpR_b(const MechTables* __restrict__ M, int s, double T) {
+  const double* a = M->cp[s];
+  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+}
+
+// Linear index of node k along axis d of the stencil through cell c
+// (periodic axes wrap).
+__device__ __forceinline__ long long node_along(const Member& G, const int c[3], int d, int k) {
+  int g[3] = {c[0], c[1], c[2]};
+  g[d] = G.bc[d][0] != 0 ? k : wrapi(k, G.n[d]);
+  return lin(G, g);
+}
+
+// Convective flux through face i+1/2 along d (i = c[d] with the other
+// coordinates of c), every variable, into out[].
+template <int NS>
+__device__ void bnd_conv_face(const Member& G, int d, const int c[3], const double* __restrict__ U,
+                              const double* __restrict__ aux, const unsigned char* __restrict__ flag, unsigned flags,
+                              double psi_c, double CT, double* out) {
+  constexpr int NV = NS + 4;
+  const long long N = G.N;
+  const int i = c[d], n = G.n[d];
+  int m = 6, start = i - 2;
+  if (G.bc[d][0] != 0 && (i < 2 || i > n - 4)) {
+    m = (i == 0 || i == n - 2) ? 2 : 4;
+    start = i - m / 2 + 1;
+  }
+  long long st[6];
+  for (int k = 0; k < m; ++k) st[k] = node_along(G, c, d, start + k);
+  const int fa = m / 2 - 1, fb = m / 2;   // the face's two nodes
+  bool te;
+  if (flags & HTR_FORCE_TENO) te = true;
+  else if (flags & HTR_FORCE_CENTRAL) te = false;
+  else {
+    int any = 0;
+    for (int k = 0; k < m; ++k) any |= flag[st[k]];
+    const double pa = aux[st[fa]], pb = aux[st[fb]];
+    te = any != 0 || fabs(pb - pa) / fmin(pa, pb) > psi_c;
+  }
+  double ud[6], p[6];
+  for (int k = 0; k < m; ++k) {
+    ud[k] = aux[(4 + d) * N + st[k]];
+    p[k] = aux[st[k]];
+  }
+  double al = 0.0;
+  if (te) {
+    al = fabs(ud[0]) + aux[N + st[0]];
+    for (int k = 1; k < m; ++k) al = fmax(al, fabs(ud[k]) + aux[N + st[k]]);
+  }
+  for (int v = 0; v < NV; ++v) {
+    double u6[6], f6[6];
+    for (int k = 0; k < m; ++k) {
+      u6[k] = U[v * N + st[k]];
+      f6[k] = node_flux<NS>(v, d, u6[k], ud[k], p[k]);
+    }
+    if (!te) {
+      if (m == 6)
+        out[v] = (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
+      else if (m == 4)
+        out[v] = (-f6[0] + 7.0 * f6[1] + 7.0 * f6[2] - f6[3]) * (1.0 / 12.0);
+      else
+        out[v] = 0.5 * (f6[0] + f6[1]);
+    } else if (m == 6) {
+      double fp[6], fm[6];
+      for (int k = 0; k < 6; ++k) {
+        fp[k] = 0.5 * (f6[k] + al * u6[k]);
+        fm[5 - k] = 0.5 * (f6[k] - al * u6[k]);
+      }
+      out[v] = (flags & HTR_WENO3Z) ? weno3z(fp) + weno3z(fm) : teno6(fp, CT) + teno6(fm, CT);
+    } else {
+      out[v] = 0.5 * (f6[fa] + f6[fb]) - 0.5 * al * (u6[fb] - u6[fa]);
+    }
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void bnd_diff_face(const MechTables* __restrict__ M, const Member& G, int d, const int c[3],
+                                              const double* __restrict__ U, const double* __restrict__ T,
+                                              const double* __restrict__ aux, const double* __restrict__ grad,
+                                              double* out) {
+  int cb[3] = {c[0], c[1], c[2]};
+  cb[d] = G.bc[d][0] != 0 ? c[d] + 1 : wrapi(c[d] + 1, G.n[d]);
+  const long long qA = lin(G, c), qB = lin(G, cb);
+  if (d == 0) diff_face<NS, 0>(M, G, c[0], qA, qB, G.N, U, T, aux, grad, out);
+  else if (d == 1) diff_face<NS, 1>(M, G, c[1], qA, qB, G.N, U, T, aux, grad, out);
+  else diff_face<NS, 2>(M, G, c[2], qA, qB, G.N, U, T, aux, grad, out);
+}
+
+template <int NS>
+__global__ __launch_bounds__(BLK) void k_bnd(const MechTables* __restrict__ M, const Member* __restrict__ mem,
+                                             CallArgs A, const double* __restrict__ U, const double* __restrict__ T,
+                                             const double* __restrict__ aux, const double* __restrict__ src,
+                                             const unsigned char* __restrict__ flag,
+                                             const double* __restrict__ grad, double* __restrict__ part,
+                                             double psi_c, double CT) {
+  constexpr int NV = NS + 4;
+  const Member& G = mem[0];
+  const long long q = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (q >= G.N) return;
+  const long long N = G.N;
+  const int c[3] = {(int)(q % G.n[0]), (int)((q / G.n[0]) % G.n[1]), (int)(q / ((long long)G.n[0] * G.n[1]))};
+  if (!in_boundary_slab(G, c)) return;
+  const unsigned flags = A.flags;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = v < NS ? src[v * N + q] : (v == NS + 3 ? src[NS * N + q] : 0.0);
+  bool onb = false;
+  double fdw[3][NS];   // diffusive species flux of the face next to a wall node, per axis
+  for (int a = 0; a < 3; ++a) {
+    if (!G.act[a]) continue;
+    const bool bnd = G.bc[a][0] != 0;
+    const bool edge = bnd && (c[a] == 0 || c[a] == G.n[a] - 1);
+    onb = onb || edge;
+    if (edge) {
+      // the node's face inside the domain, for a wall's species diffusion
+      if (!(flags & HTR_VISC_OFF) && (G.bc[a][c[a] == 0 ? 0 : 1] == HTR_BC_WALL)) {
+        int cf[3] = {c[0], c[1], c[2]};
+        if (c[a] != 0) cf[a] -= 1;
+        double fd[NV];
+        bnd_diff_face<NS>(M, G, a, cf, U, T, aux, grad, fd);
+        for (int s = 0; s < NS; ++s) fdw[a][s] = fd[s];
+      }
+      continue;
+    }
+    int cm[3] = {c[0], c[1], c[2]};
+    cm[a] = bnd ? c[a] - 1 : wrapi(c[a] - 1, G.n[a]);
+    double fcp[NV], fcm[NV], fdp[NV], fdm[NV];
+    bnd_conv_face<NS>(G, a, c, U, aux, flag, flags, psi_c, CT, fcp);
+    bnd_conv_face<NS>(G, a, cm, U, aux, flag, flags, psi_c, CT, fcm);
+    if (flags & HTR_VISC_OFF) {
+      for (int v = 0; v < NV; ++v) fdp[v] = fdm[v] = 0.0;
+    } else {
+      bnd_diff_face<NS>(M, G, a, c, U, T, aux, grad, fdp);
+      bnd_diff_face<NS>(M, G, a, cm, U, T, aux, grad, fdm);
+    }
+    const double xi = G.xin[a][c[a]];
+    for (int v = 0; v < NV; ++v) acc[v] += xi * ((fdp[v] - fdm[v]) - (fcp[v] - fcm[v]));
+  }
+  if (onb) {
+    // boundary node: characteristic treatment along every bounded axis it lies on
+    double Y[NS], rho = 0.0;
+    for (int s = 0; s < NS; ++s) rho += U[s * N + q];
+    for (int s = 0; s < NS; ++s) Y[s] = U[s * N + q] / rho;
+    const double Tq = T[q], pq = aux[q], cc = aux[N + q];
+    const double uq[3] = {aux[4 * N + q], aux[5 * N + q], aux[6 * N + q]};
+    double cpm = 0.0, iW = 0.0, hs[NS];
+    const double iT = 1.0 / Tq;
+    for (int s = 0; s < NS; ++s) {
+      cpm += Y[s] * M->RW[s] * cpR_b(M, s, Tq);
+      iW += Y[s] * M->iW[s];
+      hs[s] = M->RW[s] * Tq * hRTi(M, s, Tq, iT);
+    }
+    const double W = 1.0 / iW;
+    const double cv = cpm - RU * iW, gam = cpm / cv, cc2 = cc * cc;
+    bool held = false, holdY = false;
+    double add[NV];
+    for (int v = 0; v < NV; ++v) add[v] = 0.0;
+    const long long stride[3] = {1, G.n[0], (long long)G.n[0] * G.n[1]};
+    for (int a = 0; a < 3; ++a) {
+      if (!G.act[a] || G.bc[a][0] == 0 || !(c[a] == 0 || c[a] == G.n[a] - 1)) continue;
+      const int side = c[a] == 0 ? 0 : 1;
+      const int type = G.bc[a][side];
+      const double sgn = side ? 1.0 : -1.0;
+      const long long s1 = side ? -stride[a] : stride[a];
+      const double xi = G.xin[a][c[a]];
+      // one-sided second-order derivative along a (inward)
+      auto D = [&](double f0, double f1, double f2) {
+        return side ? xi * (3.0 * f0 - 4.0 * f1 + f2) / 2.0 : xi * (-3.0 * f0 + 4.0 * f1 - f2) / 2.0;
+      };
+      double r1 = 0.0, r2 = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        r1 += U[s * N + q + s1];
+        r2 += U[s * N + q + 2 * s1];
+      }
+      const double Dp = D(pq, aux[q + s1], aux[q + 2 * s1]);
+      const double Dr = D(rho, r1, r2);
+      double Du[3];
+      for (int mm = 0; mm < 3; ++mm)
+        Du[mm] = D(uq[mm], aux[(4 + mm) * N + q + s1], aux[(4 + mm) * N + q + 2 * s1]);
+      const double un = uq[a];
+      double L1 = (un - cc) * (Dp - rho * cc * Du[a]);
+      double L5 = (un + cc) * (Dp + rho * cc * Du[a]);
+      if (type == HTR_BC_WALL || type == HTR_BC_INFLOW) {
+        held = true;
+        if (type == HTR_BC_INFLOW) holdY = true;
+        const double Lout = side ? L5 : L1;
+        const double drho = (type == HTR_BC_INFLOW ? -(gam / cc2) : -(1.0 / cc2)) * Lout;
+        for (int s = 0; s < NS; ++s) add[s] += Y[s] * drho;
+        if (type == HTR_BC_WALL && !(flags & HTR_VISC_OFF)) {
+          const double x2 = 2.0 * xi;
+          for (int s = 0; s < NS; ++s) add[s] += (side ? -x2 : x2) * fdw[a][s];
+        }
+        continue;
+      }
+      // outflow
+      double L2 = un * (cc2 * Dr - Dp);
+      double L3 = un * Du[(a + 1) % 3], L4 = un * Du[(a + 2) % 3];
+      const double Ld = fabs(G.xnode[a][G.n[a] - 1] - G.xnode[a][0]);
+      const double Mn = fabs(un) / cc;
+      const double K = G.relax[a][side] * cc * (1.0 - Mn * Mn) / Ld;
+      const double relaxp = K * (pq - G.pinf[a][side]);
+      if (sgn * (un - cc) < 0) L1 = relaxp;
+      if (sgn * (un + cc) < 0) L5 = relaxp;
+      const bool backflow = sgn * un < 0;
+      if (backflow) { L2 = 0.0; L3 = 0.0; L4 = 0.0; }
+      const double rho_t = -(L2 + 0.5 * (L5 + L1)) / cc2;
+      const double p_t = -0.5 * (L5 + L1);
+      double u_t[3];
+      u_t[a] = -(L5 - L1) / (2.0 * rho * cc);
+      u_t[(a + 1) % 3] = -L3;
+      u_t[(a + 2) % 3] = -L4;
+      double ke = 0.0, udu = 0.0;
+      for (int mm = 0; mm < 3; ++mm) { ke += uq[mm] * uq[mm]; udu += uq[mm] * u_t[mm]; }
+      double dE = (cpm * W / RU - 1.0) * p_t + 0.5 * ke * rho_t + rho * udu;
+      for (int s = 0; s < NS; ++s) {
+        const double LY = backflow ? 0.0 : un * D(Y[s], U[s * N + q + s1] / r1, U[s * N + q + 2 * s1] / r2);
+        const double drs = Y[s] * rho_t - rho * LY;
+        add[s] += drs;
+        dE += (hs[s] - cpm * Tq * W * M->iW[s]) * drs;
+      }
+      for (int mm = 0; mm < 3; ++mm) add[NS + mm] += uq[mm] * rho_t + rho * u_t[mm];
+      add[NS + 3] += dE;
+    }
+    if (!held) {
+      for (int v = 0; v < NV; ++v) acc[v] += add[v];
+    } else {
+      double drs[NS], drho = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        drs[s] = acc[s] + add[s];
+        drho += drs[s];
+      }
+      if (holdY)
+        for (int s = 0; s < NS; ++s) drs[s] = Y[s] * drho;
+      double ke = 0.0;
+      for (int mm = 0; mm < 3; ++mm) ke += uq[mm] * uq[mm];
+      double dE = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        acc[s] = drs[s];
+        dE += (hs[s] - RU * Tq * M->iW[s] + 0.5 * ke) * drs[s];
+      }
+      for (int mm = 0; mm < 3; ++mm) acc[NS + mm] = uq[mm] * drho;
+      acc[NS + 3] = dE;
+    }
+  }
+  for (int v = 0; v < NV; ++v) part[v * N + q] = acc[v];
+}
+
+template <int NS>
+static hipError_t bnd_t(const MechTables* M, const Member* mem, int nblocks, const CallArgs& a, const double* U,
+                        const double* T, const double* aux, const double* src, const unsigned char* flag,
+                        const double* grad, double* part, double psi_c, double CT, hipStream_t s) {
+  hipLaunchKernelGGL(k_bnd<NS>, dim3(nblocks), dim3(BLK), 0, s, M, mem, a, U, T, aux, src, flag, grad, part, psi_c, CT);
+  return hipGetLastError();
+}
+
+hipError_t launch_bnd(int ns, const MechTables* M, const Member* mem, int nblocks, const CallArgs& a, const double* U,
+                      const double* T, const double* aux, const double* src, const unsigned char* flag,
+                      const double* grad, double* part, double psi_c, double CT, hipStream_t s) {
+#define C_(NS) bnd_t<NS>(M, mem, nblocks, a, U, T, aux, src, flag, grad, part, psi_c, CT, s)
+  HTR_NS_SWITCH(ns, C_);
+#undef C_
 }
 
 static int grid_of(int nblocks, int grid) { return (grid <= 0 || grid > nblocks) ? nblocks : grid; }

@@ -110,8 +110,12 @@ class Context:
 
     @classmethod
     def from_case(cls, case, flags=None):
-        return cls(case.mech, case.grid, cfl=case.cfl, theta_c=case.theta_c, psi_c=case.psi_c,
-                   teno_CT=case.teno_CT, flags=case.flags if flags is None else flags)
+        g = cls(case.mech, case.grid, cfl=case.cfl, theta_c=case.theta_c, psi_c=case.psi_c,
+                teno_CT=case.teno_CT, flags=case.flags if flags is None else flags)
+        bc = getattr(case, "bc", None)
+        if bc is not None and np.any(np.asarray(bc)):
+            htr_set_boundaries(g, bc, case.pinf, case.relax)
+        return g
 
     def close(self):
         if getattr(self, "h", None):
@@ -136,6 +140,15 @@ class Context:
 
 
 # ------------------------------------------------------------ C-name binding
+def htr_set_boundaries(ctx, bc, pinf, relax):
+    """Boundary type per axis and side (HTR_BC_*), outflow far-field
+    pressure and relaxation coefficient, each [3][2]."""
+    b = np.ascontiguousarray(np.asarray(bc, dtype=np.int32).reshape(3, 2))
+    p = np.ascontiguousarray(np.asarray(pinf, dtype=np.float64).reshape(3, 2))
+    r = np.ascontiguousarray(np.asarray(relax, dtype=np.float64).reshape(3, 2))
+    check(ctx.lib.htr_set_boundaries(ctx.h, b.ctypes.data, p.ctypes.data, r.ctypes.data))
+
+
 def htr_prim_to_cons(ctx, Y, T, p, vel, U, stream=None):
     check(ctx.lib.htr_prim_to_cons(ctx.h, _ptr(Y), _ptr(T), _ptr(p), _ptr(vel), _ptr(U), _stream(stream)))
 
