@@ -338,6 +338,23 @@ def curvilinear_measure(steps, warm=2, n=128, amp=0.25):
             "kernels": kern}
 
 
+def multifidelity_measure(hf_steps, nlf=64, n_lf=16):
+    """Multi-fidelity co-processing: the 64^3 mixing layer (HF) for hf_steps
+    SSP-RK3 steps and an LF ensemble of nlf members of n_lf^3 (the same
+    recipe, coarse grids, perturbed deposition) for 3 hf_steps steps, alone
+    and at once on two HIP streams."""
+    import synth
+    from paper_2202_02319_amd.multifidelity import Fidelities, co_process
+    hf_case = synth.case_c5()
+    e = synth.ensemble_c4(nmem=nlf, sizes=[n_lf] * nlf)
+    fid = Fidelities(hf_case, e.members, e.dlnA)
+    run = co_process(fid, hf_steps, 3 * hf_steps)
+    return {"workload": f"HF: 64^3 mixing layer, {hf_steps} RK3 steps; LF: {nlf} members of {n_lf}^3, "
+                        f"{3 * hf_steps} RK3 steps (captured graph); two HIP streams",
+            "hf_ms": round(run.hf_ms, 3), "lf_ms": round(run.lf_ms, 3), "both_ms": round(run.both_ms, 3),
+            "overlap": round(run.overlap(), 3)}
+
+
 def adjoint_measure(nsteps=50, every=10, n=64):
     """The adjoint workload: the 64^3 mixing layer, `nsteps` RK3 steps with a
     frozen dt, checkpoints every `every` steps; gradient of the time-
@@ -498,6 +515,8 @@ def main():
                     help="RK3 steps of the 256x128x128 mixing-layer measurement (0: skip)")
     ap.add_argument("--ens-steps", type=int, default=50, help="RK3 steps of the ensemble measurement (0: skip)")
     ap.add_argument("--adj-steps", type=int, default=50, help="RK3 steps of the adjoint measurement (0: skip)")
+    ap.add_argument("--mf-steps", type=int, default=10,
+                    help="HF steps of the multi-fidelity co-processing measurement (0: skip)")
     ap.add_argument("--curv-steps", type=int, default=5,
                     help="RK3 steps of the curvilinear-grid measurement (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles (no autotuning)")
@@ -557,6 +576,9 @@ def main():
         # per-member launches are latency-bound and batching pays most
         small = np.random.default_rng(12).choice(np.arange(12, 25, 4), size=64)
         out["ensemble_small"] = ensemble_measure(args.ens_steps, sizes=small)
+    if args.mf_steps > 0:
+        torch.cuda.empty_cache()
+        out["multifidelity"] = multifidelity_measure(args.mf_steps)
     if args.adj_steps > 0:
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_measure(args.adj_steps)

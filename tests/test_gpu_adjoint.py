@@ -239,3 +239,44 @@ def test_full_size_adjoint_gradient(scheme):
             assert grad[i] == pytest.approx(fd(i, 1e-6), rel=1e-5), i
         else:
             assert grad[i] == pytest.approx(fd(i, 1e-4), rel=2e-2), i
+
+
+def test_gradient_against_oracle_tangent_every_direction():
+    """Every one of the 24 parameter directions (E, centre x, y, z, ln A of
+    the 20 reactions) on the adjoint workload's recipe at 16^3 over 10 steps
+    with its frozen dt, the deposit moved into those steps (t0 = 3 dt,
+    sigma_t = 2 dt): the adjoint gradient component against the oracle's
+    forward-mode (dual-number) tangent of the whole run along that axis."""
+    case = synth.case_c5(n=16, steps=10)
+    ctx = htr.Context.from_case(case)
+    U0 = htr.cons_from_case(ctx, case)
+    T0 = dev(case.T)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    htr.htr_stable_dt(ctx, U0, T0.clone(), dt)
+    dtv = float(host(dt)[0])
+    case.laser.t0 = 3 * dtv
+    case.laser.sigma_t = 2 * dtv
+    prob = HeatReleaseProblem(ctx, U0, T0, case.laser, dtv, case.steps, checkpoint_every=5)
+    theta = torch.tensor([case.laser.E, *case.laser.center] + [0.0] * case.mech.nr, dtype=torch.float64,
+                         device="cuda")
+    th = theta.clone().requires_grad_(True)
+    J = HeatReleaseObjective.apply(th, prob)
+    J.backward()
+    grad = host(th.grad)
+    o = Oracle(case)
+    las = case.laser.as_array()
+    nth = 4 + case.mech.nr
+    scale = np.abs(grad * np.r_[case.laser.E, [case.laser.sigma_r] * 3, np.ones(case.mech.nr)]).max()
+    for i in range(nth):
+        e = np.zeros(nth)
+        e[i] = 1.0
+        U = host(prob.U0).copy()
+        dU = np.zeros_like(U)
+        T = case.T.copy()
+        Jo, dJo = 0.0, 0.0
+        for n in range(case.steps):
+            Jo, dJo = o.rk3_tangent(U, dU, T, n * dtv, dtv, las, e[:4], case.mech.lnA, e[4:], Jo, dJo)
+        assert float(J.item()) == pytest.approx(Jo, rel=1e-9)
+        # per component against the largest scaled component (a component can be near zero)
+        w = case.laser.E if i == 0 else (case.laser.sigma_r if i < 4 else 1.0)
+        assert abs(grad[i] - dJo) * w <= 1e-9 * scale, (i, grad[i], dJo)

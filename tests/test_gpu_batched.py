@@ -240,3 +240,31 @@ def test_graph_replay_follows_scheme_changes(ens):
     assert not np.array_equal(results[0][0], results[synth.FORCE_TENO][0])
     assert not np.array_equal(results[0][0], results[synth.FORCE_CENTRAL | synth.CHEM_OFF][0])
     assert np.array_equal(results[0][0], results[0][1])
+
+
+def test_multifidelity_co_processing_matches_separate_runs():
+    """An HF grid (the 64^3 mixing layer) and an LF ensemble (16 members of
+    16^3) advanced at once on two streams end bit for bit where each run
+    alone ends."""
+    from paper_2202_02319_amd.multifidelity import Fidelities, co_process
+    hf_case = synth.case_c5()
+    e = synth.ensemble_c4(nmem=16, sizes=[16] * 16)
+    fid = Fidelities(hf_case, e.members, e.dlnA)
+    fid.reset()
+    fid.hf_steps(3)
+    torch.cuda.synchronize()
+    hf_alone = fid.hf_U.clone()
+    fid.reset()
+    fid.lf_steps(6)
+    torch.cuda.synchronize()
+    lf_alone = fid.lf_U.clone()
+    fid.reset()
+    fid.hf_steps(3)
+    fid.lf_steps(6)
+    torch.cuda.synchronize()
+    fid.check()
+    assert torch.equal(fid.hf_U, hf_alone)
+    assert torch.equal(fid.lf_U, lf_alone)
+    run = co_process(fid, 3, 6)
+    print(f"HF {run.hf_ms:.2f} ms, LF {run.lf_ms:.2f} ms, both {run.both_ms:.2f} ms, overlap {run.overlap():.2f}")
+    assert run.both_ms > 0
