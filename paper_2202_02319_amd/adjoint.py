@@ -62,6 +62,31 @@ class HeatReleaseProblem:
         htr.htr_check(self.ctx)
         return J, ckpts
 
+    def switch_flips(self, theta_a, theta_b):
+        """Runs the forward at two parameter points side by side, each step
+        taped, and counts the discrete switches that differ between them:
+        (J_a, J_b, sensor flags that differ, per-face TENO cut-off patterns
+        that differ),
+        over every stage of every step.  Where both counts are zero, the two
+        runs took the same branch everywhere, so the frozen-switch adjoint is
+        the derivative of the piecewise-smooth J between them."""
+        runs = []
+        for th in (theta_a, theta_b):
+            runs.append(dict(L=self._laser_for(th), dlnA=th[4:].detach().contiguous(), U=self.U0.clone(),
+                             T=self.T0.clone(), J=torch.zeros(1, dtype=torch.float64, device=self.U0.device),
+                             work=torch.empty_like(self.work), tape=htr.new_tape(self.ctx)))
+        nflag = nteno = 0
+        for n in range(self.nsteps):
+            for r in runs:
+                r["tape"].zero_()
+                self._step(r["U"], r["T"], self.t0 + n * self.dt, r["L"], r["dlnA"], r["J"], r["work"], r["tape"])
+            fa, ta = htr.tape_switches(self.ctx, runs[0]["tape"])
+            fb, tb = htr.tape_switches(self.ctx, runs[1]["tape"])
+            nflag += int((fa != fb).sum())
+            nteno += int((ta != tb).sum())
+        htr.htr_check(self.ctx)
+        return float(runs[0]["J"].item()), float(runs[1]["J"].item()), nflag, nteno
+
     def backward(self, theta, ckpts, Jbar=1.0):
         """(dJ/dtheta, dJ/dU0) by the discrete adjoint."""
         L = self._laser_for(theta)

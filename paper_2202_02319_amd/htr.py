@@ -233,6 +233,16 @@ def new_tape(ctx, device="cuda"):
     return torch.empty((htr_tape_bytes(ctx) + 7) // 8, dtype=torch.float64, device=device)
 
 
+def tape_switches(ctx, tape):
+    """Byte views of a forward tape's discrete switches, by the layout that
+    htr_tape_bytes states: the sensor flags [3 stages][N] and the TENO
+    cut-off patterns [3 stages][3 axes][nv][N]."""
+    b = tape.view(torch.uint8)
+    N, nv = ctx.N, ctx.ns + 4
+    o = 3 * (8 + ctx.ns) * N * 8
+    return b[o:o + 3 * N], b[o + 3 * N:o + 3 * N + 9 * nv * N]
+
+
 def htr_rk3_step_taped(ctx, U, T_io, t_dev, dt_dev, compute_dt, laser, dlnA_dev, work, J_dev, tape, stream=None):
     L = make_laser(laser)
     check(ctx.lib.htr_rk3_step_taped(ctx.h, _ptr(U), _ptr(T_io), _ptr(t_dev), _ptr(dt_dev), int(compute_dt),
