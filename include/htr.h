@@ -332,7 +332,9 @@ htr_status htr_rhs_adjoint(htr_ctx* ctx, const double* U, double* T_io, double t
  * flags [N], then per stage the TENO cut-off patterns [3][nv][N] (bytes: per
  * axis, variable and face, indexed by the face's upper cell). */
 size_t htr_tape_bytes(const htr_ctx* ctx);
-/* htr_rk3_step that also records its tape (device, >= htr_tape_bytes). */
+/* htr_rk3_step that also records its tape (device, >= htr_tape_bytes).
+ * Rectilinear periodic grids of fewer than 2^31 cells; otherwise
+ * HTR_EUNSUPPORTED. */
 htr_status htr_rk3_step_taped(htr_ctx* ctx, double* U, double* T_io, double* t_dev, double* dt_dev, int compute_dt,
                               const htr_laser* laser, const double* dlnA_dev, double* work, double* J_dev,
                               void* tape, void* stream);

@@ -266,7 +266,8 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
                                                    double* s_U, double* s_L, double* s_al, unsigned char* s_fl,
                                                    unsigned char* s_te, unsigned char* s_db, double* s_ub,
                                                    double& pbu, double& pbp, double& pbc,
-                                                   const unsigned char* __restrict__ tbits) {
+                                                   const unsigned char* __restrict__ tbits,
+                                                   const double (*s_cf)[6]) {
   constexpr int NV = NS + 4;
   const int t = threadIdx.x;
   const int T[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
@@ -424,9 +425,8 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
           }
         } else {
           const unsigned bits = s_db[f];
-          double cp[6], cm[6];
-          teno6_coeffs_bits(bits & 15u, cp);
-          teno6_coeffs_bits(bits >> 4, cm);
+          const double* cp = s_cf[bits & 15u];
+          const double* cm = s_cf[bits >> 4];
           const double al = s_al[f];
           if (longax) {
             Fb += g * 0.5 * (cp[5 - k] + cm[k]);
@@ -482,6 +482,7 @@ __global__ __launch_bounds__(BLK, 2) void k_adj_conv_tiled(const Member* __restr
   __shared__ double s_ud[EXTA], s_p[EXTA], s_c[EXTA], s_U[EXTA], s_L[EXTA], s_al[FACEA];
   __shared__ unsigned char s_fl[EXTA], s_te[FACEA], s_db[FACEA];
   __shared__ double s_ub[NV * BLK];   // per-thread cotangent accumulators
+  __shared__ double s_cf[16][6];      // frozen TENO6 coefficients of every cut-off pattern
   const int m = find_member_tiled(mem, nmem, blockIdx.x);
   const Member& G = mem[m];
   const int t = threadIdx.x;
@@ -498,17 +499,18 @@ __global__ __launch_bounds__(BLK, 2) void k_adj_conv_tiled(const Member* __restr
   const double* lam = lamb + NV * G.off;
   const unsigned char* tbits = tbitsb ? tbitsb + 3LL * NV * G.off : nullptr;
   for (int v = 0; v < NV; ++v) s_ub[v * BLK + t] = 0.0;
+  if (t < 16) teno6_coeffs_bits(t, s_cf[t]);   // read after the first direction's staging barrier
   double pbu[3] = {0.0, 0.0, 0.0}, pbp = 0.0, pbc = 0.0;
   const unsigned flags = A.flags;
   if (G.act[0])
     adj_conv_tiled_dir<NS, 0>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[0], pbp, pbc, tbits);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[0], pbp, pbc, tbits, s_cf);
   if (G.act[1])
     adj_conv_tiled_dir<NS, 1>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[1], pbp, pbc, tbits);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[1], pbp, pbc, tbits, s_cf);
   if (G.act[2])
     adj_conv_tiled_dir<NS, 2>(G, o, l, gc, valid, N, U, aux, flag, lam, s, flags, psi_c, CT, s_ud, s_p, s_c, s_U, s_L,
-                              s_al, s_fl, s_te, s_db, s_ub, pbu[2], pbp, pbc, tbits);
+                              s_al, s_fl, s_te, s_db, s_ub, pbu[2], pbp, pbc, tbits, s_cf);
   if (!valid) return;
   const long long q = ((long long)gc[2] * G.n[1] + gc[1]) * G.n[0] + gc[0];
   double* ubd = ubdb + NV * G.off;

@@ -742,6 +742,7 @@ htr_status htr_rk3_step_taped(htr_ctx* c, double* U, double* T_io, double* t_dev
   if (work == U || work == T_io) return fail(HTR_EINVAL, "work must not alias U or T_io");
   if (c->curv) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for rectilinear grids");
   if (c->host_mem.bounded) return fail(HTR_EUNSUPPORTED, "the taped step (adjoint) is for periodic grids");
+  if (c->N >= (1LL << 31)) return fail(HTR_EUNSUPPORTED, "the tape indexes cells with 32 bits: N must be < 2^31");
   htr_status st = check_laser(laser);
   if (st) return st;
   Ctx C = view(c);

@@ -8,10 +8,68 @@
 
 namespace htr {
 
-// TENO6 cut-off decisions at x_{i+1/2} from f[0..5] = f_{i-2..i+3}: writes
-// the normalised weights of the four candidate stencils (d_k delta_k /
-// sum d delta) and returns the candidate values in q[4].
-__device__ __forceinline__ void teno6_core(const double f[6], double CT, double w[4], double q[4]) {
+// TENO6 cut-off decisions from the four smoothness indicators b_k and the
+// global one tau: candidate k is kept when its scale-separated weight
+// gamma_k = (1 + tau / (b_k + 1e-40))^6, normalised by the sum over the
+// four candidates, reaches C_T.  This is the reference arithmetic (every
+// quotient correctly rounded, gamma scaled by the largest r before the
+// sixth power); the result is four bits, bit k set when candidate k is kept.
+__device__ __forceinline__ unsigned teno6_pattern_exact(double b0, double b1, double b2, double b3, double tau,
+                                                        double CT) {
+  const double r0 = 1.0 + tau / (b0 + 1e-40), r1 = 1.0 + tau / (b1 + 1e-40);
+  const double r2 = 1.0 + tau / (b2 + 1e-40), r3 = 1.0 + tau / (b3 + 1e-40);
+  const double irm = 1.0 / fmax(fmax(r0, r1), fmax(r2, r3));
+  double g0 = r0 * irm, g1 = r1 * irm, g2 = r2 * irm, g3 = r3 * irm;
+  g0 = g0 * g0 * g0; g0 *= g0;
+  g1 = g1 * g1 * g1; g1 *= g1;
+  g2 = g2 * g2 * g2; g2 *= g2;
+  g3 = g3 * g3 * g3; g3 *= g3;
+  const double igs = 1.0 / (g0 + g1 + g2 + g3);
+  return (g0 * igs >= CT ? 1u : 0u) | (g1 * igs >= CT ? 2u : 0u) | (g2 * igs >= CT ? 4u : 0u) |
+         (g3 * igs >= CT ? 8u : 0u);
+}
+
+// The same decisions without a correctly rounded quotient.  The test
+// gamma_k / sum(gamma) >= C_T is the same as x_k >= C_T sum(x) for x_k =
+// (s r_k)^6 with any scale s > 0, so:
+//  - the four 1 / (b_k + 1e-40) come from one hardware reciprocal of their
+//    product (refined by two Newton steps) and three products each
+//    (Montgomery's simultaneous inversion);
+//  - s is the power of two that brings the largest r into [1/2, 1), an
+//    exact scaling;
+//  - each x_k is then within about 1e-14 (relative) of its exact value, and
+//    the reference arithmetic is within about the same distance, so where
+//    every x_k lies further than 1e-12 C_T sum(x) from C_T sum(x) both take
+//    the same decision.  Otherwise (and for a product of the b_k outside
+//    [1e-290, 1e290], or any non-finite value) the reference arithmetic
+//    decides.
+__device__ __forceinline__ unsigned teno6_pattern(double b0, double b1, double b2, double b3, double tau,
+                                                  double CT) {
+  const double D0 = b0 + 1e-40, D1 = b1 + 1e-40, D2 = b2 + 1e-40, D3 = b3 + 1e-40;
+  const double P01 = D0 * D1, P23 = D2 * D3, P = P01 * P23;
+  double inv = __builtin_amdgcn_rcp(P);
+  inv = fma(fma(-P, inv, 1.0), inv, inv);
+  inv = fma(fma(-P, inv, 1.0), inv, inv);
+  const double i01 = inv * P23, i23 = inv * P01;
+  const double r0 = fma(tau, i01 * D1, 1.0), r1 = fma(tau, i01 * D0, 1.0);
+  const double r2 = fma(tau, i23 * D3, 1.0), r3 = fma(tau, i23 * D2, 1.0);
+  const int e = -__builtin_amdgcn_frexp_exp(fmax(fmax(r0, r1), fmax(r2, r3)));
+  double x0 = __builtin_amdgcn_ldexp(r0, e), x1 = __builtin_amdgcn_ldexp(r1, e);
+  double x2 = __builtin_amdgcn_ldexp(r2, e), x3 = __builtin_amdgcn_ldexp(r3, e);
+  x0 = x0 * x0 * x0; x0 *= x0;
+  x1 = x1 * x1 * x1; x1 *= x1;
+  x2 = x2 * x2 * x2; x2 *= x2;
+  x3 = x3 * x3 * x3; x3 *= x3;
+  const double th = CT * (x0 + x1 + x2 + x3), m = 1e-12 * th;
+  const bool sure = P > 1e-290 && P < 1e290 && fabs(x0 - th) > m && fabs(x1 - th) > m && fabs(x2 - th) > m &&
+                    fabs(x3 - th) > m;
+  if (!sure) return teno6_pattern_exact(b0, b1, b2, b3, tau, CT);
+  return (x0 >= th ? 1u : 0u) | (x1 >= th ? 2u : 0u) | (x2 >= th ? 4u : 0u) | (x3 >= th ? 8u : 0u);
+}
+
+// TENO6 at x_{i+1/2} from f[0..5] = f_{i-2..i+3}: the candidate values in
+// q[4]; returns the cut-off pattern (bit k: candidate k kept).
+__device__ __forceinline__ unsigned teno6_decide(const double f[6], double CT, double q[4]) {
   q[0] = (-f[1] + 5.0 * f[2] + 2.0 * f[3]) * (1.0 / 6.0);
   q[1] = (2.0 * f[2] + 5.0 * f[3] - f[4]) * (1.0 / 6.0);
   q[2] = (2.0 * f[0] - 7.0 * f[1] + 11.0 * f[2]) * (1.0 / 6.0);
@@ -38,21 +96,23 @@ __device__ __forceinline__ void teno6_core(const double f[6], double CT, double 
                     a3 * ((3129.0 / 80.0) * a3 + (14127.0 / 224.0) * a5) + (87617.0 / 140.0) * a4 * a4 +
                     (252337135.0 / 16128.0) * a5 * a5;
   const double tau = fabs(b6 - (b1 + b2 + 4.0 * b0) * (1.0 / 6.0));
-  const double r0 = 1.0 + tau / (b0 + 1e-40), r1 = 1.0 + tau / (b1 + 1e-40);
-  const double r2 = 1.0 + tau / (b2 + 1e-40), r3 = 1.0 + tau / (b3 + 1e-40);
-  const double irm = 1.0 / fmax(fmax(r0, r1), fmax(r2, r3));
-  double g0 = r0 * irm, g1 = r1 * irm, g2 = r2 * irm, g3 = r3 * irm;
-  g0 = g0 * g0 * g0; g0 *= g0;
-  g1 = g1 * g1 * g1; g1 *= g1;
-  g2 = g2 * g2 * g2; g2 *= g2;
-  g3 = g3 * g3 * g3; g3 *= g3;
-  const double igs = 1.0 / (g0 + g1 + g2 + g3);
-  w[0] = (g0 * igs >= CT) ? 9.0 / 20.0 : 0.0;
-  w[1] = (g1 * igs >= CT) ? 3.0 / 10.0 : 0.0;
-  w[2] = (g2 * igs >= CT) ? 1.0 / 20.0 : 0.0;
-  w[3] = (g3 * igs >= CT) ? 1.0 / 5.0 : 0.0;
+  return teno6_pattern(b0, b1, b2, b3, tau, CT);
+}
+
+// Normalised weights of the kept candidates of a cut-off pattern: d_k
+// delta_k / sum d delta with d = (9/20, 3/10, 1/20, 1/5).
+__device__ __forceinline__ void teno6_weights(unsigned pat, double w[4]) {
+  w[0] = (pat & 1u) ? 9.0 / 20.0 : 0.0;
+  w[1] = (pat & 2u) ? 3.0 / 10.0 : 0.0;
+  w[2] = (pat & 4u) ? 1.0 / 20.0 : 0.0;
+  w[3] = (pat & 8u) ? 1.0 / 5.0 : 0.0;
   const double iw = 1.0 / (w[0] + w[1] + w[2] + w[3]);
   w[0] *= iw; w[1] *= iw; w[2] *= iw; w[3] *= iw;
+}
+
+// Candidate values q[4] and normalised weights w[4] of TENO6 at x_{i+1/2}.
+__device__ __forceinline__ void teno6_core(const double f[6], double CT, double w[4], double q[4]) {
+  teno6_weights(teno6_decide(f, CT, q), w);
 }
 
 // TENO6 reconstruction at x_{i+1/2} from f[0..5] = f_{i-2..i+3}.

@@ -111,9 +111,13 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
-  __shared__ double s_al[XFACE_MAX];   // LF speed of the TENO faces
-  __shared__ short s_tl[XFACE_MAX];    // the tile's TENO faces
+  __shared__ double s_al[XFACE_MAX];   // LF speed of the TENO faces, in list order
+  // the tile's TENO faces: stencil start slot (bits 0-11), axis (12-13) and
+  // face index (14-23)
+  __shared__ int s_tl[XFACE_MAX];
+  __shared__ int s_tq[TAPE ? XFACE_MAX : 1];   // taped: the face's tape index (upper cell)
   __shared__ int s_nt;
+  __shared__ double s_w[16][4];        // TENO6 normalised weights of every cut-off pattern
   // before the variable loop the same memory holds the LF node speed, the
   // pressure and the sensor flags
   double* s_spd = s_U;
@@ -228,6 +232,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     }
   }
   if (t == 0) s_nt = 0;
+  if (t < 16) teno6_weights(t, s_w[t]);
   __syncthreads();
   // face f of the list: axis, stencil start slot (stencil positions j-3..j+2
   // of the tile = box positions j..j+5 along d), stride along the axis, and
@@ -243,6 +248,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
     bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
   };
+  const int bsd1 = T[0], bsd2 = T[0] * T[1];   // stencil strides along y and z in their boxes
+  static_assert(XBOX_MAX < (1 << 12) && XFACE_MAX < (1 << 10), "TENO list packing");
   // this thread's faces: stencil start slot, stride, hybrid decision; TENO
   // faces are also listed (with their Lax-Friedrichs speed) so that each
   // variable's TENO work is spread evenly over the block
@@ -275,8 +282,15 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         double al = s_spd[e0];
 #pragma unroll
         for (int mm = 1; mm < 6; ++mm) al = fmax(al, s_spd[e0 + mm * bs]);
-        s_al[f] = al;
-        s_tl[atomicAdd(&s_nt, 1)] = (short)f;
+        const int slot = atomicAdd(&s_nt, 1);
+        s_al[slot] = al;
+        s_tl[slot] = e0 | d << 12 | f << 14;
+        if (TAPE) {
+          int g[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
+          s_tq[slot] = (int)lin(G, g);
+        }
       }
     }
   }
@@ -339,10 +353,10 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     }
     // TENO faces: the tile's list, dealt round-robin over the block
     for (int i = t; i < nteno; i += BLK) {
-      const int f = s_tl[i];
-      int d, e0, bs, fb[3];
-      face(f, d, e0, bs, fb);
-      const double al = s_al[f];
+      const int pk = s_tl[i];
+      const int e0 = pk & 0xfff, f = pk >> 14;
+      const int bs = ((pk >> 12) & 3) == 0 ? 1 : (((pk >> 12) & 3) == 1 ? bsd1 : bsd2);
+      const double al = s_al[i];
       double fp[6], fm[6];
 #pragma unroll
       for (int mm = 0; mm < 6; ++mm) {
@@ -354,20 +368,16 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         sF[f] = weno3z(fp) + weno3z(fm);
         continue;
       }
-      double wp[4], qp[4], wm[4], qm[4];
-      teno6_core(fp, CT, wp, qp);
-      teno6_core(fm, CT, wm, qm);
+      double qp[4], qm[4];
+      const unsigned pp = teno6_decide(fp, CT, qp), pm = teno6_decide(fm, CT, qm);
+      const double* wp = s_w[pp];
+      const double* wm = s_w[pm];
       sF[f] = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
               (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
       if (TAPE) {
         // the cut-off pattern: bits 0-3 the + side's kept candidates, 4-7 the - side's
-        unsigned pat = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pat |= (wp[k] > 0.0 ? 1u : 0u) << k | (wm[k] > 0.0 ? 1u : 0u) << (k + 4);
-        int g[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
-        bits[(long long)(d * NV + v) * N + lin(G, g)] = (unsigned char)pat;
+        const unsigned pat = pp | pm << 4;
+        bits[(long long)(((pk >> 12) & 3) * NV + v) * N + s_tq[i]] = (unsigned char)pat;
       }
     }
     __syncthreads();
