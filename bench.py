@@ -275,7 +275,7 @@ def ensemble_measure(steps, warm=1, sizes=None):
             "batched_over_per_member": t_m / t_b, "batched_ms_per_step": 1e3 * t_b / steps,
             "per_member_ms_per_step": 1e3 * t_m / steps,
             "tiles": {f"{n}^3": "x".join(map(str, shapes[[int(round(c.grid.N ** (1 / 3))) for c in e.members].index(n)]))
-                      for n in Ns}, "persistent_grid": grid}
+                      for n in Ns}, "persistent_grid": grid, "conv_split": htr.htr_batch_get_conv_split(b)}
 
 
 def curvilinear_measure(steps, warm=2, n=128, amp=0.25):
@@ -471,6 +471,7 @@ def single_measure(case, steps, warmup, autotune=True):
              "parts_ms": {"k_sensor": round(avg["sensor"], 4), "k_conv": round(avg["conv"], 4),
                           "k_diff": round(avg["diff"], 4)}}
     return {"ctx": ctx, "N": N, "ms": ms, "wall": wall, "value": N * 3 / (ms / 1e3), "tile": tile, "grid": grid,
+            "conv_split": htr.htr_get_conv_split(ctx),
             "avg": avg, "kt": kt, "point": point, "sweep": sweep, "J": J_timed}
 
 
@@ -553,7 +554,8 @@ def main():
                    if args.workload == "tgv128" else
                    "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser",
                    "cells": meas["N"], "species": ns, "reactions": nr, "stages_per_step": 3,
-                   "tile": "x".join(map(str, meas["tile"])), "persistent_grid": meas["grid"]},
+                   "tile": "x".join(map(str, meas["tile"])), "persistent_grid": meas["grid"],
+                   "conv_split": meas["conv_split"]},
         "roofline": roofline_of(meas, args.workload, args.steps),
     }
     del meas
@@ -565,7 +567,8 @@ def main():
             "workload": "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser deposition, "
                         f"{args.mix_steps} SSP-RK3 steps with in-step CFL dt",
             "cells": m3["N"], "steps": args.mix_steps, "value": m3["value"], "unit": "cell-stage updates/s",
-            "ms_per_step": m3["ms"], "tile": "x".join(map(str, m3["tile"])), "J": m3["J"],
+            "ms_per_step": m3["ms"], "tile": "x".join(map(str, m3["tile"])), "conv_split": m3["conv_split"],
+            "J": m3["J"],
             "roofline": roofline_of(m3, "mixing256", args.mix_steps)}
         del m3
         torch.cuda.empty_cache()

@@ -426,8 +426,9 @@ htr_status htr_tile_shape_check(const int32_t n[3], const int32_t shape[3]);
 htr_status htr_set_tiling(htr_ctx* ctx, const int32_t shape[3], int32_t grid);
 htr_status htr_get_tiling(const htr_ctx* ctx, int32_t shape[3], int32_t* grid);
 /* Times one RK3 stage (right-hand side and stage update, written to work,
- * >= htr_work_bytes) for every candidate shape and persistent grid, twice,
- * and keeps the fastest; writes the choice to shape_out[3] and grid_out
+ * >= htr_work_bytes) for every candidate shape and persistent grid (and, at
+ * grid 0, convective split; see htr_set_conv_split), twice, and keeps the
+ * fastest; writes the choice to shape_out[3] and grid_out
  * (both nullable).  U and T_io as for htr_rhs (T_io is refreshed); U is not
  * modified. */
 htr_status htr_autotune(htr_ctx* ctx, const double* U, double* T_io, double* work, void* stream,
@@ -437,9 +438,22 @@ htr_status htr_autotune(htr_ctx* ctx, const double* U, double* T_io, double* wor
 htr_status htr_batch_set_tiling(htr_batch* b, int32_t member, const int32_t shape[3], int32_t grid);
 htr_status htr_batch_get_tiling(const htr_batch* b, int32_t member, int32_t shape[3], int32_t* grid);
 /* Tunes the shape of each class of equal-size members (timed on a member
- * table holding only that class), then the batch's persistent grid; work
- * >= htr_batch_work_bytes.  Allocates and frees one small device table. */
+ * table holding only that class), then the batch's persistent grid and
+ * convective split; work >= htr_batch_work_bytes.  Allocates and frees one
+ * small device table. */
 htr_status htr_batch_autotune(htr_batch* b, const double* U, double* T_io, double* work, void* stream);
+/* The convective sweep at grid = 0 runs, by default (split = 1), as two
+ * launches: a lean variant, with fewer registers and more waves per SIMD,
+ * does the tiles none of whose faces takes the TENO path and marks the
+ * others, which the full sweep then does; split = 0 runs every tile in the
+ * full sweep.  Results are bitwise the same; htr_autotune and
+ * htr_batch_autotune time both.  HTR_EINVAL for split outside {0, 1};
+ * curvilinear contexts: HTR_EUNSUPPORTED.  Changing it discards an
+ * ensemble's captured graph. */
+htr_status htr_set_conv_split(htr_ctx* ctx, int32_t split);
+htr_status htr_get_conv_split(const htr_ctx* ctx, int32_t* split);
+htr_status htr_batch_set_conv_split(htr_batch* b, int32_t split);
+htr_status htr_batch_get_conv_split(const htr_batch* b, int32_t* split);
 
 /* Synchronises `stream`, returns the first device-side error latched since
  * the last htr_check (and clears it), or HTR_EDEVICE for a HIP error. */

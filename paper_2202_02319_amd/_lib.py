@@ -106,6 +106,10 @@ def load():
         "htr_tile_shape_check": (st, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "htr_set_tiling": (st, [vp, C.POINTER(C.c_int32), C.c_int32]),
         "htr_get_tiling": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "htr_set_conv_split": (st, [vp, C.c_int32]),
+        "htr_get_conv_split": (st, [vp, C.POINTER(C.c_int32)]),
+        "htr_batch_set_conv_split": (st, [vp, C.c_int32]),
+        "htr_batch_get_conv_split": (st, [vp, C.POINTER(C.c_int32)]),
         "htr_autotune": (st, [vp, vp, vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "htr_batch_set_tiling": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
         "htr_batch_get_tiling": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),

@@ -24,6 +24,7 @@ Ctx htr::bview(const htr_batch* b) {
   v.nblocks = b->nblocks;
   v.ntblocks = b->ntblocks;
   v.grid = b->grid;
+  v.conv_split = b->conv_split;
   v.scheme = b->ctx->scheme;
   v.total_cells = b->Ntot;
   v.timer = const_cast<Timer*>(&b->timer);

@@ -171,6 +171,7 @@ htr_status ws_alloc(Workspace& w, int ns, long long N, int nblocks, int nmem) {
       (e = hipMalloc(&w.flag, (size_t)N)) != hipSuccess ||
       (e = hipMalloc(&w.grad, sizeof(double) * 9 * N)) != hipSuccess ||
       (e = hipMalloc(&w.part, sizeof(double) * (ns + 4) * N)) != hipSuccess ||
+      (e = hipMalloc(&w.tcls, (size_t)N)) != hipSuccess ||
       (e = hipMalloc(&w.blkred, sizeof(double) * 2 * (size_t)nblocks)) != hipSuccess ||
       (e = hipMalloc(&w.status, sizeof(unsigned))) != hipSuccess ||
       (e = hipMalloc(&w.scal, sizeof(double) * 2 * (size_t)nmem)) != hipSuccess)
@@ -187,6 +188,7 @@ void ws_free(Workspace& w) {
   hipFree(w.flag);
   hipFree(w.grad);
   hipFree(w.part);
+  hipFree(w.tcls);
   hipFree(w.blkred);
   hipFree(w.status);
   hipFree(w.scal);
@@ -305,8 +307,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   {
     TimedLaunch tl(C.timer, TC_CONV, s);
     HIP_OK(launch_conv(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, w.aux, w.src, w.flag, w.part, teno_bits,
-                       C.scheme.psi_c,
-                       C.scheme.teno_CT, s));
+                       C.scheme.psi_c, C.scheme.teno_CT, C.conv_split ? w.tcls : nullptr, s));
   }
   if (C.bounded) {
     // the cells next to non-periodic boundaries: their whole right-hand side
@@ -373,6 +374,7 @@ Ctx htr::view(const htr_ctx* c) {
   v.nblocks = c->nblocks;
   v.ntblocks = c->ntblocks;
   v.grid = c->grid;
+  v.conv_split = c->conv_split;
   v.scheme = c->scheme;
   v.total_cells = c->N;
   for (int a = 0; a < 3; ++a) {

@@ -199,10 +199,12 @@ hipError_t launch_sensor(const Member* mem, int nmem, int nblocks, int grid, con
                          double* grad, double theta_c, double* theta_out, hipStream_t s);
 // bits (nullable): TENO cut-off patterns [3][nv][N] bytes, per axis, variable
 // and face (indexed by the face's upper cell); written for TENO faces only.
+// tcls: one byte per tile (at least ntblocks), the lean sweep's tile marks;
+// null: every tile in the full sweep (no lean launch).
 hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a,
                        const double* U, const double* aux, const double* src, const unsigned char* flag, double* part,
-                       unsigned char* bits, double psi_c, double CT, hipStream_t s);
+                       unsigned char* bits, double psi_c, double CT, unsigned char* tcls, hipStream_t s);
 // Right-hand side of the cells next to non-periodic boundaries (single
 // grid), written over the convective sweep's part[] for those cells.
 hipError_t launch_bnd(int ns, const MechTables* M, const Member* mem, int nblocks, const CallArgs& a, const double* U,

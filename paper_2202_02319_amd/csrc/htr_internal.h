@@ -29,6 +29,7 @@ struct Workspace {
   unsigned char* flag = nullptr;  // [N]
   double* grad = nullptr;         // [9][N] nodal velocity gradient d u_m / d x_a (row 3a + m)
   double* part = nullptr;         // [nv][N] sources + convective flux differences of a stage
+  unsigned char* tcls = nullptr;  // [N] (>= the tile count) tiles with TENO faces, marked by the lean sweep
   double* blkred = nullptr;       // [2][nblocks]
   unsigned* status = nullptr;
   double* scal = nullptr;         // [2][nmem] scratch scalars
@@ -86,6 +87,7 @@ struct Ctx {
   int nblocks = 0;
   int ntblocks = 0;               // tiled launches
   int grid = 0;                   // persistent grid of the forward kernels (0: one block per logical block)
+  int conv_split = 1;             // grid 0: central tiles in the lean convective sweep
   htr_scheme scheme{};
   long long total_cells = 0;
   int n1[3] = {1, 1, 1};          // grid of the single-member case (laser normalisation)
@@ -155,6 +157,7 @@ struct htr_ctx {
   int nblocks = 0;
   int ntblocks = 0;
   int grid = 0;                    // persistent grid (0: off)
+  int conv_split = 1;              // grid 0: lean convective sweep for the central tiles
   htr::Workspace ws;
   htr::Timer timer;
   htr::Fence fence;
@@ -179,6 +182,7 @@ struct htr_batch {
   int nblocks = 0;
   int ntblocks = 0;
   int grid = 0;                    // persistent grid (0: off)
+  int conv_split = 1;              // grid 0: lean convective sweep for the central tiles
   htr::Workspace ws;
   htr::Timer timer;
   htr::Fence fence;

@@ -33,7 +33,7 @@ size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 // Byte layout of the step's scratch for ns species and N cells in nblocks
 // per-cell blocks; returns the total.
 struct Layout {
-  size_t work, aux, src, grad, part, blkred, scal, flag, total;
+  size_t work, aux, src, grad, part, blkred, scal, flag, tcls, total;
 };
 Layout layout(int ns, long long N, int nblocks) {
   const size_t d = sizeof(double), n = (size_t)N, nv = (size_t)ns + 4;
@@ -47,6 +47,7 @@ Layout layout(int ns, long long N, int nblocks) {
   L.blkred = o; o += up(d * 2 * (size_t)nblocks);
   L.scal = o;   o += up(d * 2);
   L.flag = o;   o += up(n);
+  L.tcls = o;   o += up(n);
   L.total = o;
   return L;
 }
@@ -103,6 +104,7 @@ extern "C" htr_status htr_rk3_step_noalloc(htr_ctx* c, double* U, double* T_io, 
   w.blkred = reinterpret_cast<double*>(base + L.blkred);
   w.scal = reinterpret_cast<double*>(base + L.scal);
   w.flag = base + L.flag;
+  w.tcls = base + L.tcls;
   w.status = c->ws.status;
   double* work = reinterpret_cast<double*>(base + L.work);
   Ctx C = view(c);

@@ -102,13 +102,24 @@ constexpr int XFPT = (XFACE_MAX + BLK - 1) / BLK;
 // written once (the loading thread keeps that cell's velocity and pressure
 // in registers), and every face flux is evaluated once from them, all
 // directions together.
-template <int NS, bool TAPE>
+//
+// KIND 0: every tile.  KIND 1 (the lean variant): a tile none of whose faces
+// takes the TENO path is done here with the central faces alone (no staged
+// conserved values, no TENO state, so fewer registers and more waves per
+// SIMD); a tile with any TENO face is only marked in tcls[bl].  KIND 2: the
+// marked tiles, in full; the others return at once.
+template <int NS, bool TAPE, int KIND>
 __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem, int nmem, const CallArgs& A,
                                           const double* __restrict__ Ub, const double* __restrict__ auxb,
                                           const double* __restrict__ srcb, const unsigned char* __restrict__ flagb,
                                           double* __restrict__ partb, unsigned char* __restrict__ bitsb, double psi_c,
-                                          double CT) {
+                                          double CT, unsigned char* __restrict__ tcls) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
+  constexpr bool LEAN = KIND == 1;
+  static_assert(!(TAPE && KIND != 0), "the taped sweep runs every tile in full");
+  if constexpr (KIND == 2) {
+    if (tcls[bl] == 0) return;   // the lean variant has done this tile
+  }
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
   __shared__ double s_al[XFACE_MAX];   // LF speed of the TENO faces, in list order
@@ -208,6 +219,21 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
       as[k] = bslot(d, b[0], b[1], b[2]);
     }
   }
+  if constexpr (LEAN) {
+    // every node of the cross lies in the stencil of one of the tile's faces,
+    // so a flagged node means a TENO face: such tiles are left to the full
+    // variant after one barrier (the pressure-jump test follows below)
+    int any = (A.flags & HTR_FORCE_TENO) != 0;
+    if (!(A.flags & (HTR_FORCE_TENO | HTR_FORCE_CENTRAL))) {
+      any = flag[qc];
+#pragma unroll
+      for (int k = 0; k < APT; ++k) any |= flag[aq[k]];
+    }
+    if (__syncthreads_or(any)) {
+      if (t == 0) tcls[bl] = 1;
+      return;
+    }
+  }
   // velocity along the box axis and pressure of every staged cell, kept in
   // registers by the thread that stages it
   double cu[3], cp, hu[APT], hp[APT];
@@ -218,7 +244,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       cu[d] = aux[(4 + d) * N + qc];
-      s_spd[cs[d]] = fabs(cu[d]) + cc;
+      if constexpr (!LEAN) s_spd[cs[d]] = fabs(cu[d]) + cc;
       s_p[cs[d]] = cp;
       s_fl[cs[d]] = fc;
     }
@@ -226,13 +252,16 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     for (int k = 0; k < APT; ++k) {
       hu[k] = aux[(4 + ax[k]) * N + aq[k]];
       hp[k] = aux[aq[k]];
-      s_spd[as[k]] = fabs(hu[k]) + aux[N + aq[k]];
+      if constexpr (!LEAN) s_spd[as[k]] = fabs(hu[k]) + aux[N + aq[k]];
       s_p[as[k]] = hp[k];
       s_fl[as[k]] = flag[aq[k]];
     }
+    (void)cc;
   }
   if (t == 0) s_nt = 0;
-  if (t < 16) teno6_weights(t, s_w[t]);
+  if constexpr (!LEAN) {
+    if (t < 16) teno6_weights(t, s_w[t]);
+  }
   __syncthreads();
   // face f of the list: axis, stencil start slot (stencil positions j-3..j+2
   // of the tile = box positions j..j+5 along d), stride along the axis, and
@@ -277,7 +306,9 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         const double psi = fabs(pb - pa) / fmin(pa, pb);
         te = any != 0 || psi > psi_c;
       }
-      if (te) {
+      if (LEAN && te) {
+        atomicOr(&s_nt, 1);
+      } else if (te) {
         fte |= 1u << k;
         double al = s_spd[e0];
 #pragma unroll
@@ -316,16 +347,20 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   double* part = partb + NV * G.off;
   __syncthreads();   // the decisions have read the node speeds, pressures and flags
   const int nteno = s_nt;
+  if constexpr (LEAN) {
+    if (t == 0) tcls[bl] = nteno != 0;
+    if (nteno != 0) return;   // uniform: the full variant does this tile
+  }
 #pragma unroll 1
   for (int v = 0; v < NV; ++v) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      s_U[cs[d]] = ncore;
+      if constexpr (!LEAN) s_U[cs[d]] = ncore;
       s_Fn[cs[d]] = node_flux<NS>(v, d, ncore, cu[d], cp);
     }
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
-      s_U[as[k]] = narm[k];
+      if constexpr (!LEAN) s_U[as[k]] = narm[k];
       s_Fn[as[k]] = node_flux<NS>(v, ax[k], narm[k], hu[k], hp[k]);
     }
     const double acc0 = nsrc;
@@ -352,7 +387,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
           (f6[0] - 8.0 * f6[1] + 37.0 * f6[2] + 37.0 * f6[3] - 8.0 * f6[4] + f6[5]) * (1.0 / 60.0);
     }
     // TENO faces: the tile's list, dealt round-robin over the block
-    for (int i = t; i < nteno; i += BLK) {
+    for (int i = t; i < (LEAN ? 0 : nteno); i += BLK) {
       const int pk = s_tl[i];
       const int e0 = pk & 0xfff, f = pk >> 14;
       const int bs = ((pk >> 12) & 3) == 0 ? 1 : (((pk >> 12) & 3) == 1 ? bsd1 : bsd2);
@@ -392,21 +427,41 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
 }
 
 // MODE 0: one block per tile; 1: persistent blocks striding over the nlog
-// tiles; 2: one block per tile, also writing the TENO cut-off patterns.
+// tiles; 2: one block per tile, also writing the TENO cut-off patterns;
+// 3: one block per tile, the tiles that k_conv_lean marked in tcls.
 template <int NS, int MODE>
 __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                               int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
                                               const double* __restrict__ auxb, const double* __restrict__ srcb,
                                               const unsigned char* __restrict__ flagb, double* __restrict__ partb,
-                                              unsigned char* __restrict__ bitsb, double psi_c, double CT) {
-  if (MODE != 1) {
-    conv_tile<NS, MODE == 2>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT);
-    return;
+                                              unsigned char* __restrict__ bitsb, double psi_c, double CT,
+                                              unsigned char* __restrict__ tcls) {
+  if constexpr (MODE == 1) {
+    for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
+      conv_tile<NS, false, 0>(bl, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
+      __syncthreads();   // the next tile reuses the LDS
+    }
+  } else if constexpr (MODE == 2) {
+    conv_tile<NS, true, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
+  } else if constexpr (MODE == 3) {
+    conv_tile<NS, false, 2>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
+  } else {
+    conv_tile<NS, false, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   }
-  for (int bl = blockIdx.x; bl < nlog; bl += gridDim.x) {
-    conv_tile<NS, false>(bl, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT);
-    __syncthreads();   // the next tile reuses the LDS
-  }
+}
+
+// The lean convective sweep: the tiles without TENO faces (central fluxes
+// only), at up to four blocks per CU; marks the other tiles in tcls for
+// k_conv<NS, 3>.
+template <int NS>
+__global__ __launch_bounds__(BLK, 4) void k_conv_lean(const MechTables* __restrict__ M,
+                                                      const Member* __restrict__ mem, int nmem, CallArgs A,
+                                                      const double* __restrict__ Ub, const double* __restrict__ auxb,
+                                                      const double* __restrict__ srcb,
+                                                      const unsigned char* __restrict__ flagb,
+                                                      double* __restrict__ partb, double psi_c,
+                                                      unsigned char* __restrict__ tcls) {
+  conv_tile<NS, false, 1>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, nullptr, psi_c, 0.0, tcls);
 }
 
 // Diffusive flux at the face between nodes qA and qB = A + e_d, in the sign
@@ -914,16 +969,24 @@ static int grid_of(int nblocks, int grid) { return (grid <= 0 || grid > nblocks)
 template <int NS>
 static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid, const CallArgs& a,
                          const double* U, const double* aux, const double* src, const unsigned char* flag,
-                         double* part, unsigned char* bits, double psi_c, double CT, hipStream_t s) {
-  if (bits)   // taped: one block per tile
+                         double* part, unsigned char* bits, double psi_c, double CT, unsigned char* tcls,
+                         hipStream_t s) {
+  if (bits) {   // taped: one block per tile, every tile in full
     hipLaunchKernelGGL((k_conv<NS, 2>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, bits, psi_c, CT);
-  else if (grid < ntblocks)
+                       part, bits, psi_c, CT, tcls);
+  } else if (grid < ntblocks) {
     hipLaunchKernelGGL((k_conv<NS, 1>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, bits, psi_c, CT);
-  else
-    hipLaunchKernelGGL((k_conv<NS, 0>), dim3(grid), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, bits, psi_c, CT);
+                       part, bits, psi_c, CT, tcls);
+  } else if (!tcls) {   // every tile in the full sweep
+    hipLaunchKernelGGL((k_conv<NS, 0>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT, tcls);
+  } else {
+    // central tiles in the lean variant, then the tiles with TENO faces
+    hipLaunchKernelGGL((k_conv_lean<NS>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part,
+                       psi_c, tcls);
+    hipLaunchKernelGGL((k_conv<NS, 3>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT, tcls);
+  }
   return hipGetLastError();
 }
 
@@ -943,9 +1006,9 @@ static hipError_t diff_t(const MechTables* M, const Member* mem, int nmem, int n
 hipError_t launch_conv(int ns, const MechTables* M, const Member* mem, int nmem, int ntblocks, int grid,
                        const CallArgs& a, const double* U, const double* aux, const double* src,
                        const unsigned char* flag, double* part, unsigned char* bits, double psi_c, double CT,
-                       hipStream_t s) {
+                       unsigned char* tcls, hipStream_t s) {
   grid = grid_of(ntblocks, grid);
-#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, grid, a, U, aux, src, flag, part, bits, psi_c, CT, s)
+#define C_(NS) conv_t<NS>(M, mem, nmem, ntblocks, grid, a, U, aux, src, flag, part, bits, psi_c, CT, tcls, s)
   HTR_NS_SWITCH(ns, C_);
 #undef C_
 }

@@ -173,16 +173,22 @@ htr_status htr_autotune(htr_ctx* c, const double* U, double* T_io, double* work,
   hipStream_t s = (hipStream_t)stream;
   const int act[3] = {c->host_mem.act[0], c->host_mem.act[1], c->host_mem.act[2]};
   std::array<int, 3> best_t = {c->host_mem.tdim[0], c->host_mem.tdim[1], c->host_mem.tdim[2]};
-  int best_g = c->grid;
-  // two passes over the candidates; each candidate keeps its faster median
-  std::vector<std::pair<std::array<int, 3>, int>> cand;
+  int best_g = c->grid, best_split = c->conv_split;
+  // two passes over the candidates (shape, grid, split of the convective
+  // sweep at grid 0); each candidate keeps its faster median
+  struct Cand { std::array<int, 3> t; int g, split; };
+  std::vector<Cand> cand;
   for (auto& t : shape_candidates(act))
-    for (int g : grid_candidates()) cand.push_back({t, g});
+    for (int g : grid_candidates()) {
+      cand.push_back({t, g, 1});
+      if (g == 0) cand.push_back({t, g, 0});
+    }
   std::vector<float> tm(cand.size(), 1e30f);
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t i = 0; i < cand.size(); ++i) {
-      htr_status st = htr_set_tiling(c, cand[i].first.data(), cand[i].second);
+      htr_status st = htr_set_tiling(c, cand[i].t.data(), cand[i].g);
       if (st) return st;
+      c->conv_split = cand[i].split;
       float ms = 0.0f;
       st = time_rhs(view(c), c->ws, U, T_io, work, s, 5, &ms);
       if (st) return st;
@@ -193,10 +199,12 @@ htr_status htr_autotune(htr_ctx* c, const double* U, double* T_io, double* work,
   for (size_t i = 0; i < cand.size(); ++i) {
     if (tm[i] < best) {
       best = tm[i];
-      best_t = cand[i].first;
-      best_g = cand[i].second;
+      best_t = cand[i].t;
+      best_g = cand[i].g;
+      best_split = cand[i].split;
     }
   }
+  c->conv_split = best_split;
   htr_status st = htr_set_tiling(c, best_t.data(), best_g);
   if (st) return st;
   if (shape_out)
@@ -294,22 +302,57 @@ htr_status htr_batch_autotune(htr_batch* b, const double* U, double* T_io, doubl
   hipFree(dsub);
   if (st) return st;
   if ((st = relayout_batch(b))) return st;
-  // persistent grid of the whole batch
-  int best_g = 0;
+  // persistent grid of the whole batch (and, at grid 0, the convective
+  // sweep's split)
+  int best_g = 0, best_split = 1;
   float best = 1e30f;
   for (int g : grid_candidates()) {
-    b->grid = g;
-    float ms = 0.0f;
-    Ctx C = bview(b);
-    C.timer = nullptr;
-    if ((st = time_rhs(C, b->ws, U, T_io, work, s, 5, &ms))) return st;
-    if (ms < best) {
-      best = ms;
-      best_g = g;
+    for (int split = 1; split >= (g == 0 ? 0 : 1); --split) {
+      b->grid = g;
+      b->conv_split = split;
+      float ms = 0.0f;
+      Ctx C = bview(b);
+      C.timer = nullptr;
+      if ((st = time_rhs(C, b->ws, U, T_io, work, s, 5, &ms))) return st;
+      if (ms < best) {
+        best = ms;
+        best_g = g;
+        best_split = split;
+      }
     }
   }
   b->grid = best_g;
+  b->conv_split = best_split;
   drop_graph(b);
+  return HTR_OK;
+}
+
+htr_status htr_set_conv_split(htr_ctx* c, int32_t split) {
+  if (!c) return fail(HTR_EINVAL, "ctx is NULL");
+  if (split != 0 && split != 1) return fail(HTR_EINVAL, "split must be 0 or 1");
+  if (c->curv) return fail(HTR_EUNSUPPORTED, "the convective sweep's split applies to rectilinear grids");
+  c->conv_split = split;
+  return HTR_OK;
+}
+
+htr_status htr_get_conv_split(const htr_ctx* c, int32_t* split) {
+  if (!c || !split) return fail(HTR_EINVAL, "NULL pointer");
+  *split = c->conv_split;
+  return HTR_OK;
+}
+
+htr_status htr_batch_set_conv_split(htr_batch* b, int32_t split) {
+  if (!b) return fail(HTR_EINVAL, "batch is NULL");
+  if (split != 0 && split != 1) return fail(HTR_EINVAL, "split must be 0 or 1");
+  HIP_OK(hipDeviceSynchronize());   // a replay in flight may still use the captured graph
+  b->conv_split = split;
+  drop_graph(b);
+  return HTR_OK;
+}
+
+htr_status htr_batch_get_conv_split(const htr_batch* b, int32_t* split) {
+  if (!b || !split) return fail(HTR_EINVAL, "NULL pointer");
+  *split = b->conv_split;
   return HTR_OK;
 }
 

@@ -271,6 +271,26 @@ def htr_get_tiling(ctx):
     return tuple(sh), g.value
 
 
+def htr_set_conv_split(ctx, split):
+    check(ctx.lib.htr_set_conv_split(ctx.h, int(split)))
+
+
+def htr_get_conv_split(ctx):
+    v = C.c_int32()
+    check(ctx.lib.htr_get_conv_split(ctx.h, C.byref(v)))
+    return int(v.value)
+
+
+def htr_batch_set_conv_split(b, split):
+    check(b.lib.htr_batch_set_conv_split(b.h, int(split)))
+
+
+def htr_batch_get_conv_split(b):
+    v = C.c_int32()
+    check(b.lib.htr_batch_get_conv_split(b.h, C.byref(v)))
+    return int(v.value)
+
+
 def htr_autotune(ctx, U, T_io, work, stream=None):
     """Times every candidate tile shape and persistent grid on one RHS and
     keeps the fastest; returns (shape, grid)."""

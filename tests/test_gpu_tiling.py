@@ -1,7 +1,8 @@
 """Tile shapes, persistent grids and the autotuner.  Every face is evaluated
 once with the same arithmetic whatever the tile, so the right-hand side, RK3
 steps, the batched path and the adjoint must be bitwise identical under
-every valid shape and persistent grid; one non-default configuration is also
+every valid shape and persistent grid, and with or without the lean
+convective sweep for central tiles; one non-default configuration is also
 checked against the oracle."""
 import numpy as np
 import pytest
@@ -48,11 +49,34 @@ def test_rhs_bitwise_under_every_shape_and_grid(n, seed, flags, shapes):
     ref, ref_h = _rhs(g, U, T, case.laser)
     for shape in shapes:
         for grid in GRIDS:
-            htr.htr_set_tiling(g, shape, grid)
-            assert htr.htr_get_tiling(g) == (shape, grid)
-            out, hrr = _rhs(g, U, T, case.laser)
-            assert np.array_equal(out, ref), (shape, grid)
-            assert np.array_equal(hrr, ref_h), (shape, grid)
+            for split in ((1, 0) if grid == 0 else (1,)):
+                htr.htr_set_tiling(g, shape, grid)
+                htr.htr_set_conv_split(g, split)
+                assert htr.htr_get_tiling(g) == (shape, grid)
+                assert htr.htr_get_conv_split(g) == split
+                out, hrr = _rhs(g, U, T, case.laser)
+                assert np.array_equal(out, ref), (shape, grid, split)
+                assert np.array_equal(hrr, ref_h), (shape, grid, split)
+
+
+@pytest.mark.parametrize("flags", [0, synth.FORCE_CENTRAL, synth.FORCE_TENO, synth.FORCE_TENO | synth.WENO3Z])
+def test_lean_convective_sweep_bitwise(flags):
+    """The lean sweep (central tiles) plus the full sweep (the others)
+    against the full sweep on every tile: a 64x32x32 double mixing layer,
+    whose shear layers put TENO faces in some tiles only, and the forced
+    schemes (every tile lean, or none)."""
+    case = synth.case_c3(n=(64, 32, 32))
+    g = htr.Context.from_case(case, flags=flags)
+    U = htr.cons_from_case(g, case)
+    T = dev(case.T)
+    res = []
+    for split in (0, 1):
+        htr.htr_set_conv_split(g, split)
+        res.append(_rhs(g, U, T, case.laser))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    with pytest.raises(htr.HTRError, match="EINVAL"):
+        htr.htr_set_conv_split(g, 2)
 
 
 def test_non_default_tiling_matches_the_oracle():
@@ -141,6 +165,12 @@ def test_batched_bitwise_under_member_shapes_grid_and_autotune():
 
     def default():
         htr.htr_batch_set_tiling(b, -1, None, 0)
+        htr.htr_batch_set_conv_split(b, 1)
+
+    def unsplit():
+        default()
+        htr.htr_batch_set_conv_split(b, 0)
+        assert htr.htr_batch_get_conv_split(b) == 0
 
     def mixed():
         htr.htr_batch_set_tiling(b, -1, None, 13)
@@ -157,7 +187,7 @@ def test_batched_bitwise_under_member_shapes_grid_and_autotune():
         assert grid >= 0
 
     ref = run(default)
-    for conf in (mixed, tuned):
+    for conf in (unsplit, mixed, tuned):
         got = run(conf)
         assert np.array_equal(got[0], ref[0]), conf.__name__
         assert np.array_equal(got[1], ref[1]), conf.__name__
