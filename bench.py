@@ -393,7 +393,7 @@ def adjoint_measure(nsteps=50, every=10, n=64):
             "dJ_dE": float(gh[0]), "dJ_dcentre": [float(v) for v in gh[1:4]]}
 
 
-def single_measure(case, steps, warmup, autotune=True):
+def single_measure(case, steps, warmup, autotune=True, conv_split=None):
     """`steps` timed SSP-RK3 steps (in-step CFL dt, J accumulated) of one
     grid after `warmup` untimed ones, HIP events on the launch stream; then
     the same number of steps again with per-kernel event timing.  Returns
@@ -409,6 +409,8 @@ def single_measure(case, steps, warmup, autotune=True):
     t_dev, dt_dev, J_dev = z(), z(), z()
     work = ctx.new_work()
     laser = case.laser if case.laser.on else None
+    if conv_split is not None:
+        htr.htr_set_conv_split(ctx, conv_split)
     tile, grid = htr.htr_autotune(ctx, U, T.clone(), work) if autotune else htr.htr_get_tiling(ctx)
 
     U0, T0 = U.clone(), T.clone()
@@ -521,6 +523,9 @@ def main():
     ap.add_argument("--curv-steps", type=int, default=5,
                     help="RK3 steps of the curvilinear-grid measurement (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles (no autotuning)")
+    ap.add_argument("--conv-split", type=int, choices=(0, 1), default=None,
+                    help="with --no-autotune: 1 runs central tiles in the lean convective sweep (the default), "
+                         "0 every tile in the full sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -533,7 +538,7 @@ def main():
     import synth
 
     case = synth.case_c2() if args.workload == "tgv128" else synth.case_c3()
-    meas = single_measure(case, args.steps, args.warmup, autotune=not args.no_autotune)
+    meas = single_measure(case, args.steps, args.warmup, autotune=not args.no_autotune, conv_split=args.conv_split)
     ns, nr = case.mech.ns, case.mech.nr
     out = {
         "metric": "FP64 cell-stage updates/s (plain vs batched ensemble); adjoint/forward time",
@@ -562,7 +567,7 @@ def main():
     torch.cuda.empty_cache()
     if args.mix_steps > 0 and args.workload == "tgv128":
         c3 = synth.case_c3()
-        m3 = single_measure(c3, args.mix_steps, 2, autotune=not args.no_autotune)
+        m3 = single_measure(c3, args.mix_steps, 2, autotune=not args.no_autotune, conv_split=args.conv_split)
         out["mixing256"] = {
             "workload": "3-D periodic double mixing layer 256x128x128, 9 species, 20 reactions, laser deposition, "
                         f"{args.mix_steps} SSP-RK3 steps with in-step CFL dt",
