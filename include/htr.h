@@ -409,10 +409,12 @@ htr_status htr_batch_member_max(htr_batch* b, const double* field, double* max_d
                                 void* stream);
 
 /* ------------------------------------------------------------------------
- * Tiles, persistent launches, autotuning.  The flux sweeps work on 256-cell
- * tiles; any shape with extent 1 along inactive axes that their staging
- * buffers hold is accepted (16x4x4, 8x8x4, 8x4x8, 4x8x8 in 3-D; 16x16,
- * 32x8, 8x32, 64x4 in 2-D; 256 in 1-D).  grid > 0 launches the forward
+ * Tiles, persistent launches, autotuning.  The convective sweep works on
+ * 256-cell tiles; any shape with extent 1 along inactive axes that its
+ * staging buffers hold is accepted (16x4x4, 8x8x4, 8x4x8, 4x8x8 in 3-D;
+ * 16x16, 32x8, 8x32, 64x4 in 2-D; 256 in 1-D).  The diffusive sweep works
+ * on 192-cell tiles of a fixed shape (16x4x3 in 3-D, 16x12 in 2-D, 192 in
+ * 1-D).  grid > 0 launches the forward
  * kernels (per-cell, sensor, both sweeps) as grid persistent blocks that
  * stride over their logical blocks; grid = 0 launches one block per
  * logical block.  Results are bitwise independent of both choices (every

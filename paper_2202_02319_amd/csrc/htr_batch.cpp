@@ -23,6 +23,7 @@ Ctx htr::bview(const htr_batch* b) {
   v.nmem = b->nmem;
   v.nblocks = b->nblocks;
   v.ntblocks = b->ntblocks;
+  v.ndtblocks = b->ndtblocks;
   v.grid = b->grid;
   v.conv_split = b->conv_split;
   v.scheme = b->ctx->scheme;
@@ -80,7 +81,7 @@ htr_status htr_batch_create(htr_ctx* ctx, int32_t nmem, const htr_member_desc* m
       M.n[a] = d.n[a];
       M.act[a] = d.n[a] > 1;
     }
-    set_tiles(M, nullptr, &b->ntblocks);
+    set_tiles(M, nullptr, &b->ntblocks, &b->ndtblocks);
     b->offs[m] = off;
     off += N;
     blocks += M.nblocks;

@@ -318,7 +318,7 @@ htr_status stage(const Ctx& C, const Workspace& w, const CallArgs& a, const doub
   }
   {
     TimedLaunch tl(C.timer, TC_DIFF, s);
-    HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ntblocks, C.grid, a, U, Un, T, w.aux, w.grad, w.part, out, ca,
+    HIP_OK(launch_diff(C.ns, C.M, C.mem, C.nmem, C.ndtblocks, C.grid, a, U, Un, T, w.aux, w.grad, w.part, out, ca,
                        cb,
                        rhs_only, s));
   }
@@ -373,6 +373,7 @@ Ctx htr::view(const htr_ctx* c) {
   v.nmem = 1;
   v.nblocks = c->nblocks;
   v.ntblocks = c->ntblocks;
+  v.ndtblocks = c->ndtblocks;
   v.grid = c->grid;
   v.conv_split = c->conv_split;
   v.scheme = c->scheme;
@@ -474,7 +475,7 @@ htr_status htr_create(const htr_mech_desc* mech, const htr_grid_desc* grid, cons
   M.off = 0;
   M.block_begin = 0;
   M.nblocks = c->nblocks;
-  set_tiles(M, nullptr, &c->ntblocks);
+  set_tiles(M, nullptr, &c->ntblocks, &c->ndtblocks);
   M.laser.on = 0;
   M.dlnA = nullptr;
   if ((e = hipMalloc(&c->dmem, sizeof(Member))) != hipSuccess)

@@ -65,10 +65,14 @@ struct Member {
   long long off;              // cell offset in packed arrays
   int block_begin;            // first block of this member in per-cell launches
   int nblocks;
-  int tdim[3];                // tile of the tiled flux kernels (256 cells)
+  int tdim[3];                // tile of the convective sweep (256 cells)
   int ntile[3];               // tiles per axis
   int tblock_begin;           // first block of this member in tiled launches
   int ntblocks;
+  int dtdim[3];               // tile of the diffusive sweep (DTILE cells)
+  int dntile[3];
+  int dtblock_begin;          // first block of this member in diffusive-sweep launches
+  int ndtblocks;
   const double* xin[3];       // d(xi)/dx at nodes
   const double* xif[3];       // d(xi)/dx at faces i+1/2
   const double* xnode[3];     // node coordinates
@@ -135,17 +139,18 @@ __device__ __forceinline__ int find_member_tiled(const Member* __restrict__ mem,
   return lo;
 }
 
-// Tile origin of local tiled block bl.  Blocks are dealt to the eight XCDs
-// round-robin; the first 8*(nb/8) blocks are remapped so that each XCD works
-// on one contiguous run of tiles and neighbouring tiles share its L2.
+// Tile origin of local tiled block bl of a tiling (tile dims td, tiles per
+// axis nt, nb tiles).  Blocks are dealt to the eight XCDs round-robin; the
+// first 8*(nb/8) blocks are remapped so that each XCD works on one
+// contiguous run of tiles and neighbouring tiles share its L2.
 constexpr int TILE_ZGROUP = 4;
-__device__ __forceinline__ void tile_origin(const Member& G, int bl, int o[3]) {
-  const int nb = G.ntblocks, per = nb >> 3;
+__device__ __forceinline__ void tile_origin_of(const int td[3], const int nt[3], int nb, int bl, int o[3]) {
+  const int per = nb >> 3;
   const int lb = bl < 8 * per ? (bl & 7) * per + (bl >> 3) : bl;
   // lb -> tile: x fastest, then z within groups of TILE_ZGROUP tile layers, then
   // y, then the z group, so that tiles adjacent in y and z are processed
   // close together in time (only the last group may be thinner)
-  const int ntx = G.ntile[0], nty = G.ntile[1], ntz = G.ntile[2];
+  const int ntx = nt[0], nty = nt[1], ntz = nt[2];
   const int gz = ntz < TILE_ZGROUP ? ntz : TILE_ZGROUP;
   const int per_group = ntx * nty * gz;
   const int grp = lb / per_group;
@@ -153,9 +158,22 @@ __device__ __forceinline__ void tile_origin(const Member& G, int bl, int o[3]) {
   const int r = lb - grp * per_group;
   const int tx = r % ntx, r2 = r / ntx;
   const int tz = grp * gz + r2 % gsz, ty = r2 / gsz;
-  o[0] = tx * G.tdim[0];
-  o[1] = ty * G.tdim[1];
-  o[2] = tz * G.tdim[2];
+  o[0] = tx * td[0];
+  o[1] = ty * td[1];
+  o[2] = tz * td[2];
+}
+// The convective sweep's tiles (and the adjoint's).
+__device__ __forceinline__ void tile_origin(const Member& G, int bl, int o[3]) {
+  tile_origin_of(G.tdim, G.ntile, G.ntblocks, bl, o);
+}
+// Member of a block of the diffusive sweep.
+__device__ __forceinline__ int find_member_dtiled(const Member* __restrict__ mem, int nmem, int b) {
+  int lo = 0, hi = nmem - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (mem[mid].dtblock_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -165,7 +183,11 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 
 // Staging limits of the tiled kernels; a tile shape is accepted only if it
 // fits all of them (tile_shape_ok).
-constexpr int BLKF = 320;        // threads of the diffusive sweep: one face per thread along an axis
+// The diffusive sweep: DTILE-cell tiles in blocks of BLKF threads, one face
+// per thread along each axis (a tile has at most BLKF faces along any axis):
+// three 4-wave blocks per CU at its register count.
+constexpr int DTILE = 192;
+constexpr int BLKF = 256;
 constexpr int XBOX_MAX = 2208;   // convective cross staging: the three direction boxes (22*4*4 + 16*10*4 + 16*4*10)
 constexpr int XARM_MAX = 864;    // its halo cells: 6 per line along every axis
 constexpr int XFACE_MAX = 912;   // faces over all axes (17*4*4 + 16*5*4 + 16*4*5)
@@ -214,9 +236,11 @@ hipError_t launch_diff(int ns, const MechTables* M, const Member* mem, int nmem,
                        const CallArgs& a,
                        const double* U, const double* Un, const double* T, const double* aux, const double* grad,
                        const double* part, double* out, double ca, double cb, int rhs_only, hipStream_t s);
-// Tile shape of member M (shape == nullptr: the default for its active
-// axes); appends its tiles to the running count *tblocks.
-void set_tiles(Member& M, const int* shape, int* tblocks);
+// Tile shape of member M's convective sweep (shape == nullptr: the default
+// for its active axes), appending its tiles to the running count *tblocks;
+// and its diffusive sweep's tiles (a fixed shape for its active axes),
+// appended to *dtblocks.
+void set_tiles(Member& M, const int* shape, int* tblocks, int* dtblocks);
 // Whether a tile shape suits a member with active axes act (message on failure).
 bool tile_shape_ok(const int act[3], const int shape[3], const char** why);
 // Default tile shape for the active axes.

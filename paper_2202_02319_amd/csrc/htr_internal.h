@@ -85,7 +85,8 @@ struct Ctx {
   const Member* mem = nullptr;
   int nmem = 1;
   int nblocks = 0;
-  int ntblocks = 0;               // tiled launches
+  int ntblocks = 0;               // tiled launches (convective sweep)
+  int ndtblocks = 0;              // diffusive-sweep launches
   int grid = 0;                   // persistent grid of the forward kernels (0: one block per logical block)
   int conv_split = 1;             // grid 0: central tiles in the lean convective sweep
   htr_scheme scheme{};
@@ -156,6 +157,7 @@ struct htr_ctx {
   long long N = 0;
   int nblocks = 0;
   int ntblocks = 0;
+  int ndtblocks = 0;
   int grid = 0;                    // persistent grid (0: off)
   int conv_split = 1;              // grid 0: lean convective sweep for the central tiles
   htr::Workspace ws;
@@ -181,6 +183,7 @@ struct htr_batch {
   long long Ntot = 0;
   int nblocks = 0;
   int ntblocks = 0;
+  int ndtblocks = 0;
   int grid = 0;                    // persistent grid (0: off)
   int conv_split = 1;              // grid 0: lean convective sweep for the central tiles
   htr::Workspace ws;

@@ -8,10 +8,11 @@
 // second-order central differences for the diffusive fluxes; Methods › Solver eqs.
 // (1)-(3), (5), (6) for the flux vectors.
 //
-// Two tiled kernels per stage, one block per 256-cell tile: k_conv (sources
-// and convective flux differences, with the tile and its halo staged in
-// LDS) and k_diff (diffusive flux differences and the stage update).  Every
-// face is evaluated once, so the scheme is exactly conservative.
+// Two tiled kernels per stage: k_conv (sources and convective flux
+// differences, one block per 256-cell tile with the tile and its halo staged
+// in LDS) and k_diff (diffusive flux differences and the stage update, one
+// block per 192-cell tile of its own).  Every face is evaluated once, so the
+// scheme is exactly conservative.
 
 #include <math.h>
 
@@ -52,7 +53,6 @@ bool tile_shape_ok(const int act[3], const int t[3], const char** why) {
       box += cs * (t[d] + 6);
       arms += 6 * cs;
       faces += cs * (t[d] + 1);
-      if (!w && cs * (t[d] + 1) > BLKF) w = "too many faces along one axis for the diffusive sweep";
       if (!w && (cs * (t[d] + 10) > EXTA || cs * (t[d] + 5) > FACEA))
         w = "halo box too large for the convective adjoint";
     }
@@ -63,7 +63,26 @@ bool tile_shape_ok(const int act[3], const int t[3], const char** why) {
   return w == nullptr;
 }
 
-void set_tiles(Member& M, const int* shape, int* tblocks) {
+// The diffusive sweep's tile for the active axes: 16 x 4 x 3 in 3-D (204,
+// 240 and 256 faces), 16 x 12 over the two active axes of 2-D grids (204 and
+// 208), 192 along a 1-D grid.
+static void diff_tile_shape(const int act[3], int t[3]) {
+  const int na = act[0] + act[1] + act[2];
+  t[0] = t[1] = t[2] = 1;
+  if (na == 3) {
+    t[0] = 16; t[1] = 4; t[2] = 3;
+  } else if (na == 2) {
+    int k = 0;
+    for (int a = 0; a < 3; ++a)
+      if (act[a]) t[a] = k++ == 0 ? 16 : 12;
+  } else if (na == 1) {
+    for (int a = 0; a < 3; ++a) t[a] = act[a] ? DTILE : 1;
+  } else {
+    t[0] = DTILE;
+  }
+}
+
+void set_tiles(Member& M, const int* shape, int* tblocks, int* dtblocks) {
   const int act[3] = {M.act[0], M.act[1], M.act[2]};
   int t[3];
   if (shape) {
@@ -80,6 +99,17 @@ void set_tiles(Member& M, const int* shape, int* tblocks) {
   M.tblock_begin = *tblocks;
   M.ntblocks = nb;
   *tblocks += nb;
+  int dt[3];
+  diff_tile_shape(act, dt);
+  int nd = 1;
+  for (int a = 0; a < 3; ++a) {
+    M.dtdim[a] = dt[a];
+    M.dntile[a] = (M.n[a] + dt[a] - 1) / dt[a];
+    nd *= M.dntile[a];
+  }
+  M.dtblock_begin = *dtblocks;
+  M.ndtblocks = nd;
+  *dtblocks += nd;
 }
 
 __device__ __forceinline__ long long lin(const Member& G, const int g[3]) {
@@ -567,7 +597,7 @@ __device__ __forceinline__ void diff_dir(const MechTables* __restrict__ M, const
                                          double (*s_Fd)[BLKF], double* acc) {
   constexpr int NV = NS + 4;
   const int t = threadIdx.x;
-  int FB[3] = {G.tdim[0], G.tdim[1], G.tdim[2]};
+  int FB[3] = {G.dtdim[0], G.dtdim[1], G.dtdim[2]};
   FB[d] += 1;
   const int F = FB[0] * FB[1] * FB[2];
   if (t < F) {
@@ -599,8 +629,9 @@ __device__ __forceinline__ void diff_dir(const MechTables* __restrict__ M, const
 
 // Diffusive flux differences (each face once, exchanged through LDS) added
 // to part, then the SSP-RK3 stage combination (or dU/dt when rhs_only).
-// BLKF threads: the first BLK own the tile's cells; every thread owns one
-// face per direction (a tile has at most BLKF faces along any axis).
+// The diffusive sweep's own tiles (dtdim, DTILE cells): BLKF threads, the
+// first DTILE own the tile's cells, and every thread owns one face per
+// direction (a tile has at most BLKF faces along any axis).
 template <int NS>
 __device__ __forceinline__ void diff_tile(int bl, const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                           int nmem, const CallArgs& A, const double* __restrict__ Ub,
@@ -610,15 +641,15 @@ __device__ __forceinline__ void diff_tile(int bl, const MechTables* __restrict__
                                           int rhs_only) {
   constexpr int NV = NS + 4, NAUX = 7 + NS;
   __shared__ double s_Fd[NV][BLKF];
-  const int m = find_member_tiled(mem, nmem, bl);
+  const int m = find_member_dtiled(mem, nmem, bl);
   const Member& G = mem[m];
   const int t = threadIdx.x;
   int o[3];
-  tile_origin(G, bl - G.tblock_begin, o);
-  const int T0 = G.tdim[0], T1 = G.tdim[1];
+  tile_origin_of(G.dtdim, G.dntile, G.ndtblocks, bl - G.dtblock_begin, o);
+  const int T0 = G.dtdim[0], T1 = G.dtdim[1];
   const int l[3] = {t % T0, (t / T0) % T1, t / (T0 * T1)};
   const int gc[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-  const bool valid = t < BLK && gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
+  const bool valid = t < DTILE && gc[0] < G.n[0] && gc[1] < G.n[1] && gc[2] < G.n[2];
   const long long N = G.N;
   const double* U = Ub + NV * G.off;
   const double* T = Tb + G.off;

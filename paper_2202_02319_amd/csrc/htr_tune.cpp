@@ -105,9 +105,10 @@ htr_status upload_ctx_member(htr_ctx* c) {
 // Re-derives every member's tiled-block range from its shape, uploads the table.
 htr_status relayout_batch(htr_batch* b) {
   b->ntblocks = 0;
+  b->ndtblocks = 0;
   for (auto& M : b->host) {
     const int t[3] = {M.tdim[0], M.tdim[1], M.tdim[2]};
-    set_tiles(M, t, &b->ntblocks);
+    set_tiles(M, t, &b->ntblocks, &b->ndtblocks);
   }
   HIP_OK(hipDeviceSynchronize());
   HIP_OK(hipMemcpy(b->dmem, b->host.data(), sizeof(Member) * b->nmem, hipMemcpyHostToDevice));
@@ -154,7 +155,8 @@ htr_status htr_set_tiling(htr_ctx* c, const int32_t shape[3], int32_t grid) {
     default_tile_shape(act, t);
   }
   c->ntblocks = 0;
-  set_tiles(c->host_mem, t, &c->ntblocks);
+  c->ndtblocks = 0;
+  set_tiles(c->host_mem, t, &c->ntblocks, &c->ndtblocks);
   c->grid = grid;
   return upload_ctx_member(c);
 }
@@ -265,13 +267,13 @@ htr_status htr_batch_autotune(htr_batch* b, const double* U, double* T_io, doubl
     for (auto& t : shape_candidates(act)) {
       // a member table with only this class, its block ranges renumbered
       std::vector<Member> sub;
-      int nb = 0, ntb = 0;
+      int nb = 0, ntb = 0, ndtb = 0;
       long long cells = 0;
       for (int m : members) {
         Member M = b->host[m];
         M.block_begin = nb;
         nb += M.nblocks;
-        set_tiles(M, t.data(), &ntb);
+        set_tiles(M, t.data(), &ntb, &ndtb);
         cells += M.N;
         sub.push_back(M);
       }
@@ -284,6 +286,7 @@ htr_status htr_batch_autotune(htr_batch* b, const double* U, double* T_io, doubl
       C.nmem = (int)sub.size();
       C.nblocks = nb;
       C.ntblocks = ntb;
+      C.ndtblocks = ndtb;
       C.grid = 0;
       C.timer = nullptr;
       C.total_cells = cells;
