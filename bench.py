@@ -375,11 +375,11 @@ def adjoint_measure(nsteps=50, every=10, n=64):
     prob = HeatReleaseProblem(ctx, U0, T0, case.laser, float(dt.item()), nsteps, checkpoint_every=every)
     theta = torch.tensor([case.laser.E, *case.laser.center] + [0.0] * case.mech.nr, dtype=torch.float64,
                          device="cuda")
-    J, ck = prob.forward(theta)            # warm-up
+    J, ck = prob.forward(theta, keep_last=True)            # warm-up
     prob.backward(theta, ck)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J, ck = prob.forward(theta)
+    J, ck = prob.forward(theta, keep_last=True)   # as the autograd function runs it
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     g, _ = prob.backward(theta, ck)

@@ -4,8 +4,9 @@ adjoint, behind a torch.autograd.Function with step checkpointing.
 J(theta) = sum_steps dt sum_k b_k sum_cells dV HRR(U^(k), t_k) for a fixed
 number of SSP-RK3 steps with a frozen step dt, theta = (E, centre x, y, z,
 ln A offsets of every reaction).  The forward pass keeps the state every
-`checkpoint_every` steps; the backward pass re-runs each segment keeping its
-stage states and forward tapes and walks it in reverse with
+`checkpoint_every` steps, and it takes the last segment's steps with their
+tapes and keeps them; the backward pass re-runs every other segment keeping
+its stage states and forward tapes, and walks each segment in reverse with
 htr_rk3_step_adjoint.  All arithmetic runs in the HIP library; torch holds
 the buffers.
 """
@@ -48,18 +49,29 @@ class HeatReleaseProblem:
         else:
             htr.htr_rk3_step_taped(self.ctx, U, T, t_dev, dt_dev, 0, L, dlnA, work, J, tape)
 
-    def forward(self, theta):
-        """J and the checkpoints [(step, U, T)]."""
+    def forward(self, theta, keep_last=False):
+        """J and the checkpoints [(step, U, T)].  keep_last: the last
+        segment's steps are taken with their tapes, kept for the backward
+        pass, which then does not re-run that segment."""
         L = self._laser_for(theta)
         dlnA = theta[4:].detach().contiguous()
         U, T = self.U0.clone(), self.T0.clone()
         J = torch.zeros(1, dtype=torch.float64, device=U.device)
         ckpts = []
+        last0 = ((self.nsteps - 1) // self.K) * self.K if self.nsteps > 0 else 0
+        self._kept = None
         for n in range(self.nsteps):
             if n % self.K == 0:
                 ckpts.append((n, U.clone(), T.clone()))
-            self._step(U, T, self.t0 + n * self.dt, L, dlnA, J)
+            if keep_last and n >= last0:
+                i = n - last0
+                self.seg_states[i].copy_(U)
+                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J, self.seg_stages[i], self.seg_tapes[i])
+            else:
+                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J)
         htr.htr_check(self.ctx)
+        if keep_last and self.nsteps > 0:
+            self._kept = (ckpts, last0, T.clone())
         return J, ckpts
 
     def switch_flips(self, theta_a, theta_b):
@@ -94,14 +106,19 @@ class HeatReleaseProblem:
         Ubar = torch.zeros_like(self.U0)
         pbar = torch.zeros(self.nth, dtype=torch.float64, device=self.U0.device)
         J = torch.zeros(1, dtype=torch.float64, device=self.U0.device)
+        kept = self._kept if (getattr(self, "_kept", None) and self._kept[0] is ckpts) else None
         for (n0, Uc, Tc) in reversed(ckpts):
             n1 = min(n0 + self.K, self.nsteps)
-            U, T = Uc.clone(), Tc.clone()
-            # re-run the segment, keeping each step's start state, stage
-            # states and tape (per-cell fields, T and sensor flags per stage)
-            for i, n in enumerate(range(n0, n1)):
-                self.seg_states[i].copy_(U)
-                self._step(U, T, self.t0 + n * self.dt, L, dlnA, J, self.seg_stages[i], self.seg_tapes[i])
+            if kept is not None and n0 == kept[1]:
+                # the forward pass kept this segment's states and tapes
+                T = kept[2].clone()
+            else:
+                U, T = Uc.clone(), Tc.clone()
+                # re-run the segment, keeping each step's start state, stage
+                # states and tape (per-cell fields, T and sensor flags per stage)
+                for i, n in enumerate(range(n0, n1)):
+                    self.seg_states[i].copy_(U)
+                    self._step(U, T, self.t0 + n * self.dt, L, dlnA, J, self.seg_stages[i], self.seg_tapes[i])
             for i in reversed(range(n1 - n0)):
                 n = n0 + i
                 htr.htr_rk3_step_adjoint(self.ctx, self.seg_states[i], self.seg_stages[i], T, self.t0 + n * self.dt,
@@ -116,7 +133,7 @@ class HeatReleaseObjective(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, problem):
-        J, ckpts = problem.forward(theta)
+        J, ckpts = problem.forward(theta, keep_last=True)
         ctx.problem = problem
         ctx.ckpts = ckpts
         ctx.save_for_backward(theta)
