@@ -517,23 +517,38 @@ template <class S> static S teno6(const S* f, double CT, double* detail = nullpt
   S q2 = (2.0 * f[0] - 7.0 * f[1] + 11.0 * f[2]) / 6.0;         // {i-2,i-1,i}
   S q3 = (3.0 * f[2] + 13.0 * f[3] - 5.0 * f[4] + f[5]) / 12.0; // {i..i+3}
   // smoothness indicators: sum over derivative orders of the cell-i integral
-  const double c0a = g[1] - 2 * g[2] + g[3], c0b = g[1] - g[3];
-  const double c1a = g[2] - 2 * g[3] + g[4], c1b = 3 * g[2] - 4 * g[3] + g[4];
-  const double c2a = g[0] - 2 * g[1] + g[2], c2b = g[0] - 4 * g[1] + 3 * g[2];
-  const double c3a = -11 * g[2] + 18 * g[3] - 9 * g[4] + 2 * g[5];
-  const double c3b = 2 * g[2] - 5 * g[3] + 4 * g[4] - g[5];
-  const double c3c = -g[2] + 3 * g[3] - 3 * g[4] + g[5];
+  // of the squared derivatives of each candidate polynomial.  Those
+  // derivatives are combinations of the undivided differences of the stencil
+  // values (first d, second D, third T, fourth Q, fifth P), so the
+  // indicators and the six-point polynomial's coefficients are written with
+  // the differences taken first: no cancellation between the stencil values
+  // themselves enters them.
+  double d[5], D[4], T[3], Q[2];
+  for (int k = 0; k < 5; ++k) d[k] = g[k + 1] - g[k];
+  for (int k = 0; k < 4; ++k) D[k] = d[k + 1] - d[k];
+  for (int k = 0; k < 3; ++k) T[k] = D[k + 1] - D[k];
+  for (int k = 0; k < 2; ++k) Q[k] = T[k + 1] - T[k];
+  const double P = Q[1] - Q[0];
+  // three-point candidates: the second difference (a) and the first
+  // derivative at the centre of cell i (b), up to sign
+  const double c0a = D[1], c0b = d[1] + d[2];               // {i-1,i,i+1}
+  const double c1a = D[2], c1b = 3 * d[2] - d[3];           // {i,i+1,i+2}
+  const double c2a = D[0], c2b = 3 * d[1] - d[0];           // {i-2,i-1,i}
+  // four-point candidate: its first, second and third derivative terms
+  const double c3a = 11 * d[2] - 7 * d[3] + 2 * d[4];
+  const double c3b = D[2] - T[2];
+  const double c3c = T[2];
   double b0 = 13.0 / 12.0 * c0a * c0a + 0.25 * c0b * c0b;
   double b1 = 13.0 / 12.0 * c1a * c1a + 0.25 * c1b * c1b;
   double b2 = 13.0 / 12.0 * c2a * c2a + 0.25 * c2b * c2b;
   double b3 = 1.0 / 36.0 * c3a * c3a + 13.0 / 12.0 * c3b * c3b + 781.0 / 720.0 * c3c * c3c;
   // six-point polynomial p(x) = sum a_k x^k with cell averages f (x in cell
   // widths, origin at the centre of cell i); beta6 as a quadratic form in a_1..a_5.
-  double a1 = (341 * g[0] - 2785 * g[1] - 2590 * g[2] + 6670 * g[3] - 1895 * g[4] + 259 * g[5]) / 5760.0;
-  double a2 = -(g[0] - 12 * g[1] + 22 * g[2] - 12 * g[3] + g[4]) / 16.0;
-  double a3 = -(5 * g[0] + 11 * g[1] - 70 * g[2] + 94 * g[3] - 47 * g[4] + 7 * g[5]) / 144.0;
-  double a4 = (g[0] - 4 * g[1] + 6 * g[2] - 4 * g[3] + g[4]) / 24.0;
-  double a5 = -(g[0] - 5 * g[1] + 10 * g[2] - 10 * g[3] + 5 * g[4] - g[5]) / 120.0;
+  double a1 = (-341 * d[0] + 2444 * d[1] + 5034 * d[2] - 1636 * d[3] + 259 * d[4]) / 5760.0;
+  double a2 = (8 * D[1] - Q[0]) / 16.0;
+  double a3 = (5 * T[0] + 26 * T[1] - 7 * T[2]) / 144.0;
+  double a4 = Q[0] / 24.0;
+  double a5 = P / 120.0;
   double b6 = a1 * a1 + 0.5 * a1 * a3 + 0.125 * a1 * a5 + 13.0 / 3.0 * a2 * a2 + 21.0 / 5.0 * a2 * a4 +
               3129.0 / 80.0 * a3 * a3 + 14127.0 / 224.0 * a3 * a5 + 87617.0 / 140.0 * a4 * a4 +
               252337135.0 / 16128.0 * a5 * a5;

@@ -31,11 +31,13 @@ def sym():
     st = {0: [-1, 0, 1], 1: [0, 1, 2], 2: [-2, -1, 0], 3: [0, 1, 2, 3]}
     P = {k: _poly(v) for k, v in st.items()}
     P6 = _poly([-2, -1, 0, 1, 2, 3])
-    B = {k: sp.lambdify(F, _beta(P[k], len(st[k]))) for k in st}
-    B6 = sp.lambdify(F, _beta(P6, 6))
+    Bx = {k: _beta(P[k], len(st[k])) for k in st}
+    B6x = _beta(P6, 6)
+    B = {k: sp.lambdify(F, Bx[k]) for k in st}
+    B6 = sp.lambdify(F, B6x)
     Q = {k: sp.lambdify(F, P[k].subs(X, sp.Rational(1, 2))) for k in st}
     Q6 = P6.subs(X, sp.Rational(1, 2))
-    return dict(B=B, B6=B6, Q=Q, Q6=Q6)
+    return dict(B=B, B6=B6, Q=Q, Q6=Q6, Bx=Bx, B6x=B6x)
 
 
 def test_linear_weights_give_central6(sym):
@@ -59,6 +61,26 @@ def test_smoothness_indicators_match_definition(sym):
             assert abs(det["beta"][k] - ref) <= 1e-12 * max(abs(ref), 1e-300) + 1e-300
         ref6 = sym["B6"](*f)
         assert abs(det["beta6"] - ref6) <= 1e-11 * abs(ref6)
+
+
+def test_smoothness_indicators_of_nearly_uniform_data(sym):
+    """Data that varies by 1e-9 of its size: the indicators (~1e-18 f^2)
+    keep their relative accuracy against the exact value of the definition
+    at the same (exactly represented) data, because they are formed from the
+    differences of the stencil values, which are exact here.  Sums of
+    multiples of the values themselves (-11 f_i + 18 f_{i+1} - ...) carry the
+    rounding of those products: 1e-8 to 1e-6 of the four-point indicator and
+    of beta6 on this data."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        f = 1.0 + 1e-9 * rng.normal(size=6)
+        _, det = teno6_detail(f)
+        exact = {F[i]: sp.Rational(float(f[i])) for i in range(6)}
+        for k in range(4):
+            ref = float(sym["Bx"][k].subs(exact))
+            assert abs(det["beta"][k] - ref) <= 1e-12 * ref, (k, det["beta"][k], ref)
+        ref6 = float(sym["B6x"].subs(exact))
+        assert abs(det["beta6"] - ref6) <= 1e-12 * ref6
 
 
 def test_smooth_data_uses_all_stencils_and_is_sixth_order(sym):
