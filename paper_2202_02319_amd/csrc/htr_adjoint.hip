@@ -395,15 +395,15 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
       }
       const int e0 = fe0[k];
       const double al = s_al[f];
-      double fp[6], fm[6];
+      double hp[6], hm[6], e4[4];
 #pragma unroll
       for (int mm = 0; mm < 6; ++mm) {
         const int e = e0 + mm * bs;
         const double u6 = s_U[e], f6 = node_flux<NS>(v, d, u6, s_ud[e], s_p[e]);
-        fp[mm] = 0.5 * (f6 + al * u6);
-        fm[5 - mm] = 0.5 * (f6 - al * u6);
+        hp[mm] = fma(al, u6, f6);
+        hm[5 - mm] = fma(-al, u6, f6);
       }
-      s_db[f] = (unsigned char)(teno6_bits(fp, CT) | (teno6_bits(fm, CT) << 4));
+      s_db[f] = (unsigned char)(teno6_decide(hp, CT, e4) | (teno6_decide(hm, CT, e4) << 4));
     }
     __syncthreads();
     if (valid) {

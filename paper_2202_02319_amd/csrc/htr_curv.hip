@@ -337,13 +337,13 @@ __global__ __launch_bounds__(BLK) void k_curv_conv(const Member* __restrict__ me
         for (int m = 0; m < 6; ++m) sacc += cc[m] * f[m];
         res = sacc / 60.0;
       } else {
-        double fp[6], fmr[6];
+        double hp[6], hmr[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-          fp[m] = 0.5 * (f[m] + alpha * Uv[m]);
-          fmr[5 - m] = 0.5 * (f[m] - alpha * Uv[m]);
+          hp[m] = fma(alpha, Uv[m], f[m]);
+          hmr[5 - m] = fma(-alpha, Uv[m], f[m]);
         }
-        res = weno ? weno3z(fp) + weno3z(fmr) : teno6(fp, CT) + teno6(fmr, CT);
+        res = weno ? weno3z_h(hp) + weno3z_h(hmr) : teno6_h(hp, CT) + teno6_h(hmr, CT);
       }
       out[v * N + qf] = res;
     }

@@ -31,18 +31,16 @@ __device__ __forceinline__ unsigned teno6_pattern_exact(double b0, double b1, do
 
 // The same decisions without a correctly rounded quotient.  The test
 // gamma_k / sum(gamma) >= C_T is the same as x_k >= C_T sum(x) for x_k =
-// (s r_k)^6 with any scale s > 0, so:
+// (s r_k)^6 with any scale s > 0, here s = 1, so:
 //  - the four 1 / (b_k + 1e-40) come from one hardware reciprocal of their
 //    product (refined by two Newton steps) and three products each
 //    (Montgomery's simultaneous inversion);
-//  - s is the power of two that brings the largest r into [1/2, 1), an
-//    exact scaling;
-//  - each x_k is then within about 1e-14 (relative) of its exact value, and
-//    the reference arithmetic is within about the same distance, so where
-//    every x_k lies further than 1e-12 C_T sum(x) from C_T sum(x) both take
-//    the same decision.  Otherwise (and for a product of the b_k outside
-//    [1e-290, 1e290], or any non-finite value) the reference arithmetic
-//    decides.
+//  - each x_k = r_k^6 (r_k >= 1) is then within about 1e-14 (relative) of
+//    its exact value, and the reference arithmetic is within about the same
+//    distance, so where every x_k lies further than 1e-12 C_T sum(x) from
+//    C_T sum(x) both take the same decision.  Otherwise (and for a product of
+//    the b_k outside [1e-290, 1e290], a sum of the x_k beyond 1e300, or any
+//    non-finite value) the reference arithmetic decides.
 __device__ __forceinline__ unsigned teno6_pattern(double b0, double b1, double b2, double b3, double tau,
                                                   double CT) {
   const double D0 = b0 + 1e-40, D1 = b1 + 1e-40, D2 = b2 + 1e-40, D3 = b3 + 1e-40;
@@ -51,47 +49,57 @@ __device__ __forceinline__ unsigned teno6_pattern(double b0, double b1, double b
   inv = fma(fma(-P, inv, 1.0), inv, inv);
   inv = fma(fma(-P, inv, 1.0), inv, inv);
   const double i01 = inv * P23, i23 = inv * P01;
-  const double r0 = fma(tau, i01 * D1, 1.0), r1 = fma(tau, i01 * D0, 1.0);
-  const double r2 = fma(tau, i23 * D3, 1.0), r3 = fma(tau, i23 * D2, 1.0);
-  const int e = -__builtin_amdgcn_frexp_exp(fmax(fmax(r0, r1), fmax(r2, r3)));
-  double x0 = __builtin_amdgcn_ldexp(r0, e), x1 = __builtin_amdgcn_ldexp(r1, e);
-  double x2 = __builtin_amdgcn_ldexp(r2, e), x3 = __builtin_amdgcn_ldexp(r3, e);
+  double x0 = fma(tau, i01 * D1, 1.0), x1 = fma(tau, i01 * D0, 1.0);
+  double x2 = fma(tau, i23 * D3, 1.0), x3 = fma(tau, i23 * D2, 1.0);
   x0 = x0 * x0 * x0; x0 *= x0;
   x1 = x1 * x1 * x1; x1 *= x1;
   x2 = x2 * x2 * x2; x2 *= x2;
   x3 = x3 * x3 * x3; x3 *= x3;
-  const double th = CT * (x0 + x1 + x2 + x3), m = 1e-12 * th;
-  const bool sure = P > 1e-290 && P < 1e290 && fabs(x0 - th) > m && fabs(x1 - th) > m && fabs(x2 - th) > m &&
-                    fabs(x3 - th) > m;
+  const double sx = x0 + x1 + x2 + x3, th = CT * sx, m = 1e-12 * th;
+  const bool sure = P > 1e-290 && P < 1e290 && sx < 1e300 && fabs(x0 - th) > m && fabs(x1 - th) > m &&
+                    fabs(x2 - th) > m && fabs(x3 - th) > m;
   if (!sure) return teno6_pattern_exact(b0, b1, b2, b3, tau, CT);
   return (x0 >= th ? 1u : 0u) | (x1 >= th ? 2u : 0u) | (x2 >= th ? 4u : 0u) | (x3 >= th ? 8u : 0u);
 }
 
-// TENO6 at x_{i+1/2} from f[0..5] = f_{i-2..i+3}: the candidate values in
-// q[4]; returns the cut-off pattern (bit k: candidate k kept).
-__device__ __forceinline__ unsigned teno6_decide(const double f[6], double CT, double q[4]) {
-  q[0] = (-f[1] + 5.0 * f[2] + 2.0 * f[3]) * (1.0 / 6.0);
-  q[1] = (2.0 * f[2] + 5.0 * f[3] - f[4]) * (1.0 / 6.0);
-  q[2] = (2.0 * f[0] - 7.0 * f[1] + 11.0 * f[2]) * (1.0 / 6.0);
-  q[3] = (3.0 * f[2] + 13.0 * f[3] - 5.0 * f[4] + f[5]) * (1.0 / 12.0);
-  const double s0a = f[1] - 2.0 * f[2] + f[3], s0b = f[1] - f[3];
-  const double s1a = f[2] - 2.0 * f[3] + f[4], s1b = 3.0 * f[2] - 4.0 * f[3] + f[4];
-  const double s2a = f[0] - 2.0 * f[1] + f[2], s2b = f[0] - 4.0 * f[1] + 3.0 * f[2];
-  const double s3a = -11.0 * f[2] + 18.0 * f[3] - 9.0 * f[4] + 2.0 * f[5];
-  const double s3b = 2.0 * f[2] - 5.0 * f[3] + 4.0 * f[4] - f[5];
-  const double s3c = -f[2] + 3.0 * f[3] - 3.0 * f[4] + f[5];
-  const double b0 = (13.0 / 12.0) * s0a * s0a + 0.25 * s0b * s0b;
-  const double b1 = (13.0 / 12.0) * s1a * s1a + 0.25 * s1b * s1b;
-  const double b2 = (13.0 / 12.0) * s2a * s2a + 0.25 * s2b * s2b;
-  const double b3 = (1.0 / 36.0) * s3a * s3a + (13.0 / 12.0) * s3b * s3b + (781.0 / 720.0) * s3c * s3c;
+// TENO6 at x_{i+1/2} for one side of the Lax-Friedrichs flux splitting,
+// from h[0..5] = 2 f_{i-2..i+3}: the splitting's factor 1/2 is folded into
+// the constants (powers of two), so every smoothness indicator below is that
+// of f.  The candidates' indicators, the six-point polynomial's coefficients
+// and the candidates themselves are all formed from the undivided
+// differences of h along the stencil (first d, second D, third T, fourth Q,
+// fifth P), which they share; each is the indicator's defining formula
+// rewritten exactly (an identity in rational arithmetic), with the
+// differences taken first.  Returns the cut-off pattern (bit k: candidate k
+// kept); e[k] are the candidates' increments over f_i: q_k = h_2/2 + e_k/12
+// for k < 3 and q_3 = h_2/2 + e_3/24.
+__device__ __forceinline__ unsigned teno6_decide(const double h[6], double CT, double e[4]) {
+  const double d0 = h[1] - h[0], d1 = h[2] - h[1], d2 = h[3] - h[2], d3 = h[4] - h[3], d4 = h[5] - h[4];
+  const double D0 = d1 - d0, D1 = d2 - d1, D2 = d3 - d2, D3 = d4 - d3;
+  const double T0 = D1 - D0, T1 = D2 - D1, T2 = D3 - D2;
+  const double Q0 = T1 - T0, P0 = (T2 - T1) - Q0;
+  // candidates: q_0 on {i-1, i, i+1}, q_1 on {i, i+1, i+2}, q_2 on
+  // {i-2, i-1, i}, q_3 on {i, ..., i+3}
+  e[0] = fma(2.0, d2, d1);
+  e[1] = fma(4.0, d2, -d3);
+  e[2] = fma(5.0, d1, -2.0 * d0);
+  e[3] = fma(9.0, d2, fma(-4.0, d3, d4));
+  // smoothness of the three-point candidates: their second difference and
+  // their one-sided first difference at the centre
+  const double s0b = d1 + d2, s1b = fma(3.0, d2, -d3), s2b = fma(3.0, d1, -d0);
+  const double b0 = (13.0 / 48.0) * (D1 * D1) + (1.0 / 16.0) * (s0b * s0b);
+  const double b1 = (13.0 / 48.0) * (D2 * D2) + (1.0 / 16.0) * (s1b * s1b);
+  const double b2 = (13.0 / 48.0) * (D0 * D0) + (1.0 / 16.0) * (s2b * s2b);
+  // of the four-point candidate: its first, second and third derivative terms
+  const double s3a = fma(11.0, d2, fma(-7.0, d3, 2.0 * d4)), s3b = D2 - T2;
+  const double b3 = (1.0 / 144.0) * (s3a * s3a) + (13.0 / 48.0) * (s3b * s3b) + (781.0 / 2880.0) * (T2 * T2);
   // six-point polynomial coefficients (origin at the centre of cell i)
-  const double a1 = (341.0 * f[0] - 2785.0 * f[1] - 2590.0 * f[2] + 6670.0 * f[3] - 1895.0 * f[4] + 259.0 * f[5]) *
-                    (1.0 / 5760.0);
-  const double a2 = -(f[0] - 12.0 * f[1] + 22.0 * f[2] - 12.0 * f[3] + f[4]) * (1.0 / 16.0);
-  const double a3 = -(5.0 * f[0] + 11.0 * f[1] - 70.0 * f[2] + 94.0 * f[3] - 47.0 * f[4] + 7.0 * f[5]) *
-                    (1.0 / 144.0);
-  const double a4 = (f[0] - 4.0 * f[1] + 6.0 * f[2] - 4.0 * f[3] + f[4]) * (1.0 / 24.0);
-  const double a5 = -(f[0] - 5.0 * f[1] + 10.0 * f[2] - 10.0 * f[3] + 5.0 * f[4] - f[5]) * (1.0 / 120.0);
+  const double a1 = (-341.0 / 11520.0) * d0 + (2444.0 / 11520.0) * d1 + (5034.0 / 11520.0) * d2 +
+                    (-1636.0 / 11520.0) * d3 + (259.0 / 11520.0) * d4;
+  const double a2 = fma(8.0, D1, -Q0) * (1.0 / 32.0);
+  const double a3 = (5.0 / 288.0) * T0 + (26.0 / 288.0) * T1 + (-7.0 / 288.0) * T2;
+  const double a4 = Q0 * (1.0 / 48.0);
+  const double a5 = P0 * (1.0 / 240.0);
   const double b6 = a1 * (a1 + 0.5 * a3 + 0.125 * a5) + a2 * ((13.0 / 3.0) * a2 + (21.0 / 5.0) * a4) +
                     a3 * ((3129.0 / 80.0) * a3 + (14127.0 / 224.0) * a5) + (87617.0 / 140.0) * a4 * a4 +
                     (252337135.0 / 16128.0) * a5 * a5;
@@ -110,29 +118,19 @@ __device__ __forceinline__ void teno6_weights(unsigned pat, double w[4]) {
   w[0] *= iw; w[1] *= iw; w[2] *= iw; w[3] *= iw;
 }
 
-// Candidate values q[4] and normalised weights w[4] of TENO6 at x_{i+1/2}.
-__device__ __forceinline__ void teno6_core(const double f[6], double CT, double w[4], double q[4]) {
-  teno6_weights(teno6_decide(f, CT, q), w);
+// The weights of teno6_decide's increments e[k] in the face value:
+// sum_k w_k q_k = h_2/2 + sum_k W_k e_k (the normalised weights sum to one).
+__device__ __forceinline__ void teno6_wface(unsigned pat, double W[4]) {
+  teno6_weights(pat, W);
+  W[0] *= 1.0 / 12.0; W[1] *= 1.0 / 12.0; W[2] *= 1.0 / 12.0; W[3] *= 1.0 / 24.0;
 }
 
-// TENO6 reconstruction at x_{i+1/2} from f[0..5] = f_{i-2..i+3}.
-__device__ __forceinline__ double teno6(const double f[6], double CT) {
-  double w[4], q[4];
-  teno6_core(f, CT, w, q);
-  return w[0] * q[0] + w[1] * q[1] + w[2] * q[2] + w[3] * q[3];
-}
-
-// The reconstruction with its cut-offs frozen is linear in f: c[m] are the
-// coefficients of f[m] (the candidate stencils combined with the weights).
-__device__ __forceinline__ void teno6_coeffs(const double f[6], double CT, double c[6]) {
-  double w[4], q[4];
-  teno6_core(f, CT, w, q);
-  c[0] = w[2] * (2.0 / 6.0);
-  c[1] = w[0] * (-1.0 / 6.0) + w[2] * (-7.0 / 6.0);
-  c[2] = w[0] * (5.0 / 6.0) + w[1] * (2.0 / 6.0) + w[2] * (11.0 / 6.0) + w[3] * (3.0 / 12.0);
-  c[3] = w[0] * (2.0 / 6.0) + w[1] * (5.0 / 6.0) + w[3] * (13.0 / 12.0);
-  c[4] = w[1] * (-1.0 / 6.0) + w[3] * (-5.0 / 12.0);
-  c[5] = w[3] * (1.0 / 12.0);
+// TENO6 reconstruction at x_{i+1/2} of one side of the split, from
+// h = 2 f_{i-2..i+3}.
+__device__ __forceinline__ double teno6_h(const double h[6], double CT) {
+  double e[4], W[4];
+  teno6_wface(teno6_decide(h, CT, e), W);
+  return 0.5 * h[2] + (W[0] * e[0] + W[1] * e[1] + W[2] * e[2] + W[3] * e[3]);
 }
 
 // Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges) from f_{i-1},
@@ -150,15 +148,17 @@ __device__ __forceinline__ double weno3z(const double f[6]) {
   return (a0 * q0 + a1 * q1) / (a0 + a1);
 }
 
-// Cut-off pattern of teno6_core as four bits (bit k: candidate k kept).
-__device__ __forceinline__ unsigned teno6_bits(const double f[6], double CT) {
-  double w[4], q[4];
-  teno6_core(f, CT, w, q);
-  return (w[0] > 0.0 ? 1u : 0u) | (w[1] > 0.0 ? 2u : 0u) | (w[2] > 0.0 ? 4u : 0u) | (w[3] > 0.0 ? 8u : 0u);
+// WENO3-Z of one side of the split from h = 2 f (the stencil values halved
+// first, as the scheme takes them).
+__device__ __forceinline__ double weno3z_h(const double h[6]) {
+  double f[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) f[m] = 0.5 * h[m];
+  return weno3z(f);
 }
 
 // Linear coefficients of the frozen reconstruction from its cut-off bits
-// (the same normalised weights teno6_core produces for that pattern).
+// (the normalised weights of that pattern; coefficients of f, not of h).
 __device__ __forceinline__ void teno6_coeffs_bits(unsigned b, double c[6]) {
   double w0 = (b & 1u) ? 9.0 / 20.0 : 0.0, w1 = (b & 2u) ? 3.0 / 10.0 : 0.0;
   double w2 = (b & 4u) ? 1.0 / 20.0 : 0.0, w3 = (b & 8u) ? 1.0 / 5.0 : 0.0;
