@@ -158,7 +158,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   __shared__ int s_tl[XFACE_MAX];
   __shared__ int s_tq[TAPE ? XFACE_MAX : 1];   // taped: the face's tape index (upper cell)
   __shared__ int s_nt;
-  __shared__ double s_w[16][4];        // TENO6 normalised weights of every cut-off pattern
+  __shared__ double s_w[16][4];        // TENO6 face weights of every cut-off pattern
   // before the variable loop the same memory holds the LF node speed, the
   // pressure and the sensor flags
   double* s_spd = s_U;
@@ -290,7 +290,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   }
   if (t == 0) s_nt = 0;
   if constexpr (!LEAN) {
-    if (t < 16) teno6_weights(t, s_w[t]);
+    if (t < 16) teno6_wface(t, s_w[t]);
   }
   __syncthreads();
   // face f of the list: axis, stencil start slot (stencil positions j-3..j+2
@@ -422,23 +422,24 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
       const int e0 = pk & 0xfff, f = pk >> 14;
       const int bs = ((pk >> 12) & 3) == 0 ? 1 : (((pk >> 12) & 3) == 1 ? bsd1 : bsd2);
       const double al = s_al[i];
-      double fp[6], fm[6];
+      // the two sides of the split, without their factor 1/2
+      double hp[6], hm[6];
 #pragma unroll
       for (int mm = 0; mm < 6; ++mm) {
         const double f6 = s_Fn[e0 + mm * bs], u6 = s_U[e0 + mm * bs];
-        fp[mm] = 0.5 * (f6 + al * u6);
-        fm[5 - mm] = 0.5 * (f6 - al * u6);
+        hp[mm] = fma(al, u6, f6);
+        hm[5 - mm] = fma(-al, u6, f6);
       }
       if (flags & HTR_WENO3Z) {
-        sF[f] = weno3z(fp) + weno3z(fm);
+        sF[f] = weno3z_h(hp) + weno3z_h(hm);
         continue;
       }
-      double qp[4], qm[4];
-      const unsigned pp = teno6_decide(fp, CT, qp), pm = teno6_decide(fm, CT, qm);
+      double ep[4], em[4];
+      const unsigned pp = teno6_decide(hp, CT, ep), pm = teno6_decide(hm, CT, em);
       const double* wp = s_w[pp];
       const double* wm = s_w[pm];
-      sF[f] = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
-              (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
+      sF[f] = 0.5 * (hp[2] + hm[2]) + ((wp[0] * ep[0] + wp[1] * ep[1] + wp[2] * ep[2] + wp[3] * ep[3]) +
+                                       (wm[0] * em[0] + wm[1] * em[1] + wm[2] * em[2] + wm[3] * em[3]));
       if (TAPE) {
         // the cut-off pattern: bits 0-3 the + side's kept candidates, 4-7 the - side's
         const unsigned pat = pp | pm << 4;
@@ -456,9 +457,15 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   }
 }
 
+// tiles per block of the marked-tile pass of the split convective sweep
+constexpr int CONV_MARKED_TPB = 16;
+
 // MODE 0: one block per tile; 1: persistent blocks striding over the nlog
 // tiles; 2: one block per tile, also writing the TENO cut-off patterns;
-// 3: one block per tile, the tiles that k_conv_lean marked in tcls.
+// 3: the tiles that k_conv_lean marked in tcls: block b takes tiles b + j G
+// (j < CONV_MARKED_TPB, G the grid size, a multiple of eight so that a tile
+// runs on the XCD of its one-block-per-tile slot), reads their marks at once
+// (one load per lane of the first wave) and runs the marked ones.
 template <int NS, int MODE>
 __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                               int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
@@ -474,7 +481,20 @@ __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ 
   } else if constexpr (MODE == 2) {
     conv_tile<NS, true, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   } else if constexpr (MODE == 3) {
-    conv_tile<NS, false, 2>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
+    static_assert(CONV_MARKED_TPB <= 64, "one wave reads the marks");
+    __shared__ unsigned long long s_mark;
+    const int j = threadIdx.x;
+    const int blj = blockIdx.x + j * gridDim.x;
+    const bool mk = j < CONV_MARKED_TPB && blj < nlog && tcls[blj] != 0;
+    const unsigned long long ball = __ballot(mk);
+    if (j == 0) s_mark = ball;
+    __syncthreads();
+    for (unsigned long long mask = s_mark; mask != 0; mask &= mask - 1) {
+      const int jj = __ffsll(mask) - 1;
+      conv_tile<NS, false, 2>(blockIdx.x + jj * gridDim.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c,
+                              CT, tcls);
+      __syncthreads();   // the next tile reuses the LDS
+    }
   } else {
     conv_tile<NS, false, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   }
@@ -795,12 +815,12 @@ __device__ void bnd_conv_face(const Member& G, int d, const int c[3], const doub
       else
         out[v] = 0.5 * (f6[0] + f6[1]);
     } else if (m == 6) {
-      double fp[6], fm[6];
+      double hp[6], hm[6];
       for (int k = 0; k < 6; ++k) {
-        fp[k] = 0.5 * (f6[k] + al * u6[k]);
-        fm[5 - k] = 0.5 * (f6[k] - al * u6[k]);
+        hp[k] = fma(al, u6[k], f6[k]);
+        hm[5 - k] = fma(-al, u6[k], f6[k]);
       }
-      out[v] = (flags & HTR_WENO3Z) ? weno3z(fp) + weno3z(fm) : teno6(fp, CT) + teno6(fm, CT);
+      out[v] = (flags & HTR_WENO3Z) ? weno3z_h(hp) + weno3z_h(hm) : teno6_h(hp, CT) + teno6_h(hm, CT);
     } else {
       out[v] = 0.5 * (f6[fa] + f6[fb]) - 0.5 * al * (u6[fb] - u6[fa]);
     }
@@ -1015,8 +1035,9 @@ static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int n
     // central tiles in the lean variant, then the tiles with TENO faces
     hipLaunchKernelGGL((k_conv_lean<NS>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part,
                        psi_c, tcls);
-    hipLaunchKernelGGL((k_conv<NS, 3>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
-                       part, bits, psi_c, CT, tcls);
+    const int g3 = ((ntblocks + CONV_MARKED_TPB - 1) / CONV_MARKED_TPB + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_conv<NS, 3>), dim3(g3 < ntblocks ? g3 : ntblocks), dim3(BLK), 0, s, M, mem, nmem,
+                       ntblocks, a, U, aux, src, flag, part, bits, psi_c, CT, tcls);
   }
   return hipGetLastError();
 }
