@@ -153,10 +153,11 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   // one spare slot past every box: a write target for threads without a halo cell
   __shared__ double s_U[XBOX_MAX + 1], s_Fn[XBOX_MAX + 1], s_F[2][XFACE_MAX];
   __shared__ double s_al[XFACE_MAX];   // LF speed of the TENO faces, in list order
-  // the tile's TENO faces: stencil start slot (bits 0-11), axis (12-13) and
-  // face index (14-23)
-  __shared__ int s_tl[XFACE_MAX];
-  __shared__ int s_tq[TAPE ? XFACE_MAX : 1];   // taped: the face's tape index (upper cell)
+  // the tile's TENO faces: stencil start slot (bits 0-11), face index
+  // (12-21) and stencil stride in its box (22-31)
+  __shared__ unsigned s_tl[XFACE_MAX];
+  __shared__ int s_tq[TAPE ? XFACE_MAX : 1];             // taped: the face's tape index (upper cell)
+  __shared__ unsigned char s_td[TAPE ? XFACE_MAX : 1];   // taped: the face's axis
   __shared__ int s_nt;
   __shared__ double s_w[16][4];        // TENO6 face weights of every cut-off pattern
   // before the variable loop the same memory holds the LF node speed, the
@@ -307,8 +308,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     const int B0 = T[0] + (d == 0 ? 6 : 0), B1 = T[1] + (d == 1 ? 6 : 0);
     bs = d == 0 ? 1 : (d == 1 ? B0 : B0 * B1);
   };
-  const int bsd1 = T[0], bsd2 = T[0] * T[1];   // stencil strides along y and z in their boxes
-  static_assert(XBOX_MAX < (1 << 12) && XFACE_MAX < (1 << 10), "TENO list packing");
+  // a stride is at most T[0] T[1] <= BLK cells
+  static_assert(XBOX_MAX < (1 << 12) && XFACE_MAX < (1 << 10) && BLK < (1 << 10), "TENO list packing");
   // this thread's faces: stencil start slot, stride, hybrid decision; TENO
   // faces are also listed (with their Lax-Friedrichs speed) so that each
   // variable's TENO work is spread evenly over the block
@@ -345,12 +346,13 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         for (int mm = 1; mm < 6; ++mm) al = fmax(al, s_spd[e0 + mm * bs]);
         const int slot = atomicAdd(&s_nt, 1);
         s_al[slot] = al;
-        s_tl[slot] = e0 | d << 12 | f << 14;
+        s_tl[slot] = (unsigned)e0 | (unsigned)f << 12 | (unsigned)bs << 22;
         if (TAPE) {
           int g[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) g[c] = wrapi(o[c] + fb[c], G.n[c]);
           s_tq[slot] = (int)lin(G, g);
+          s_td[slot] = (unsigned char)d;
         }
       }
     }
@@ -418,9 +420,8 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
     }
     // TENO faces: the tile's list, dealt round-robin over the block
     for (int i = t; i < (LEAN ? 0 : nteno); i += BLK) {
-      const int pk = s_tl[i];
-      const int e0 = pk & 0xfff, f = pk >> 14;
-      const int bs = ((pk >> 12) & 3) == 0 ? 1 : (((pk >> 12) & 3) == 1 ? bsd1 : bsd2);
+      const unsigned pk = s_tl[i];
+      const int e0 = pk & 0xfffu, f = (pk >> 12) & 0x3ffu, bs = pk >> 22;
       const double al = s_al[i];
       // the two sides of the split, without their factor 1/2
       double hp[6], hm[6];
@@ -443,7 +444,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
       if (TAPE) {
         // the cut-off pattern: bits 0-3 the + side's kept candidates, 4-7 the - side's
         const unsigned pat = pp | pm << 4;
-        bits[(long long)(((pk >> 12) & 3) * NV + v) * N + s_tq[i]] = (unsigned char)pat;
+        bits[(long long)(s_td[i] * NV + v) * N + s_tq[i]] = (unsigned char)pat;
       }
     }
     __syncthreads();
