@@ -393,7 +393,7 @@ def adjoint_measure(nsteps=50, every=10, n=64):
             "dJ_dE": float(gh[0]), "dJ_dcentre": [float(v) for v in gh[1:4]]}
 
 
-def single_measure(case, steps, warmup, autotune=True, conv_split=None):
+def single_measure(case, steps, warmup, autotune=True, conv_split=None, tile=None):
     """`steps` timed SSP-RK3 steps (in-step CFL dt, J accumulated) of one
     grid after `warmup` untimed ones, HIP events on the launch stream; then
     the same number of steps again with per-kernel event timing.  Returns
@@ -411,6 +411,8 @@ def single_measure(case, steps, warmup, autotune=True, conv_split=None):
     laser = case.laser if case.laser.on else None
     if conv_split is not None:
         htr.htr_set_conv_split(ctx, conv_split)
+    if tile is not None:
+        htr.htr_set_tiling(ctx, tile, 0)
     tile, grid = htr.htr_autotune(ctx, U, T.clone(), work) if autotune else htr.htr_get_tiling(ctx)
 
     U0, T0 = U.clone(), T.clone()
@@ -526,6 +528,8 @@ def main():
     ap.add_argument("--conv-split", type=int, choices=(0, 1), default=None,
                     help="with --no-autotune: 1 runs central tiles in the lean convective sweep (the default), "
                          "0 every tile in the full sweep")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="with --no-autotune: the convective tile shape, e.g. 8x8x4 (default 16x4x4)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -538,7 +542,9 @@ def main():
     import synth
 
     case = synth.case_c2() if args.workload == "tgv128" else synth.case_c3()
-    meas = single_measure(case, args.steps, args.warmup, autotune=not args.no_autotune, conv_split=args.conv_split)
+    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
+    meas = single_measure(case, args.steps, args.warmup, autotune=not args.no_autotune, conv_split=args.conv_split,
+                          tile=tile)
     ns, nr = case.mech.ns, case.mech.nr
     out = {
         "metric": "FP64 cell-stage updates/s (plain vs batched ensemble); adjoint/forward time",

@@ -458,15 +458,9 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   }
 }
 
-// tiles per block of the marked-tile pass of the split convective sweep
-constexpr int CONV_MARKED_TPB = 16;
-
 // MODE 0: one block per tile; 1: persistent blocks striding over the nlog
 // tiles; 2: one block per tile, also writing the TENO cut-off patterns;
-// 3: the tiles that k_conv_lean marked in tcls: block b takes tiles b + j G
-// (j < CONV_MARKED_TPB, G the grid size, a multiple of eight so that a tile
-// runs on the XCD of its one-block-per-tile slot), reads their marks at once
-// (one load per lane of the first wave) and runs the marked ones.
+// 3: one block per tile, the tiles that k_conv_lean marked in tcls.
 template <int NS, int MODE>
 __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ M, const Member* __restrict__ mem,
                                               int nmem, int nlog, CallArgs A, const double* __restrict__ Ub,
@@ -482,20 +476,7 @@ __global__ __launch_bounds__(BLK, 2) void k_conv(const MechTables* __restrict__ 
   } else if constexpr (MODE == 2) {
     conv_tile<NS, true, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   } else if constexpr (MODE == 3) {
-    static_assert(CONV_MARKED_TPB <= 64, "one wave reads the marks");
-    __shared__ unsigned long long s_mark;
-    const int j = threadIdx.x;
-    const int blj = blockIdx.x + j * gridDim.x;
-    const bool mk = j < CONV_MARKED_TPB && blj < nlog && tcls[blj] != 0;
-    const unsigned long long ball = __ballot(mk);
-    if (j == 0) s_mark = ball;
-    __syncthreads();
-    for (unsigned long long mask = s_mark; mask != 0; mask &= mask - 1) {
-      const int jj = __ffsll(mask) - 1;
-      conv_tile<NS, false, 2>(blockIdx.x + jj * gridDim.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c,
-                              CT, tcls);
-      __syncthreads();   // the next tile reuses the LDS
-    }
+    conv_tile<NS, false, 2>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   } else {
     conv_tile<NS, false, 0>(blockIdx.x, mem, nmem, A, Ub, auxb, srcb, flagb, partb, bitsb, psi_c, CT, tcls);
   }
@@ -1036,9 +1017,8 @@ static hipError_t conv_t(const MechTables* M, const Member* mem, int nmem, int n
     // central tiles in the lean variant, then the tiles with TENO faces
     hipLaunchKernelGGL((k_conv_lean<NS>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, a, U, aux, src, flag, part,
                        psi_c, tcls);
-    const int g3 = ((ntblocks + CONV_MARKED_TPB - 1) / CONV_MARKED_TPB + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_conv<NS, 3>), dim3(g3 < ntblocks ? g3 : ntblocks), dim3(BLK), 0, s, M, mem, nmem,
-                       ntblocks, a, U, aux, src, flag, part, bits, psi_c, CT, tcls);
+    hipLaunchKernelGGL((k_conv<NS, 3>), dim3(ntblocks), dim3(BLK), 0, s, M, mem, nmem, ntblocks, a, U, aux, src, flag,
+                       part, bits, psi_c, CT, tcls);
   }
   return hipGetLastError();
 }
