@@ -395,7 +395,7 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
       }
       const int e0 = fe0[k];
       const double al = s_al[f];
-      double hp[6], hm[6], e4[4];
+      double hp[6], hm[6], q4[4];
 #pragma unroll
       for (int mm = 0; mm < 6; ++mm) {
         const int e = e0 + mm * bs;
@@ -403,7 +403,7 @@ __device__ __forceinline__ void adj_conv_tiled_dir(const Member& G, const int o[
         hp[mm] = fma(al, u6, f6);
         hm[5 - mm] = fma(-al, u6, f6);
       }
-      s_db[f] = (unsigned char)(teno6_decide(hp, CT, e4) | (teno6_decide(hm, CT, e4) << 4));
+      s_db[f] = (unsigned char)(teno6_decide(hp, CT, q4) | (teno6_decide(hm, CT, q4) << 4));
     }
     __syncthreads();
     if (valid) {

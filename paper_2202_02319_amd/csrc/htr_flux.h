@@ -64,42 +64,35 @@ __device__ __forceinline__ unsigned teno6_pattern(double b0, double b1, double b
 
 // TENO6 at x_{i+1/2} for one side of the Lax-Friedrichs flux splitting,
 // from h[0..5] = 2 f_{i-2..i+3}: the splitting's factor 1/2 is folded into
-// the constants (powers of two), so every smoothness indicator below is that
-// of f.  The candidates' indicators, the six-point polynomial's coefficients
-// and the candidates themselves are all formed from the undivided
-// differences of h along the stencil (first d, second D, third T, fourth Q,
-// fifth P), which they share; each is the indicator's defining formula
-// rewritten exactly (an identity in rational arithmetic), with the
-// differences taken first.  Returns the cut-off pattern (bit k: candidate k
-// kept); e[k] are the candidates' increments over f_i: q_k = h_2/2 + e_k/12
-// for k < 3 and q_3 = h_2/2 + e_3/24.
-__device__ __forceinline__ unsigned teno6_decide(const double h[6], double CT, double e[4]) {
-  const double d0 = h[1] - h[0], d1 = h[2] - h[1], d2 = h[3] - h[2], d3 = h[4] - h[3], d4 = h[5] - h[4];
-  const double D0 = d1 - d0, D1 = d2 - d1, D2 = d3 - d2, D3 = d4 - d3;
-  const double T0 = D1 - D0, T1 = D2 - D1, T2 = D3 - D2;
-  const double Q0 = T1 - T0, P0 = (T2 - T1) - Q0;
-  // candidates: q_0 on {i-1, i, i+1}, q_1 on {i, i+1, i+2}, q_2 on
-  // {i-2, i-1, i}, q_3 on {i, ..., i+3}
-  e[0] = fma(2.0, d2, d1);
-  e[1] = fma(4.0, d2, -d3);
-  e[2] = fma(5.0, d1, -2.0 * d0);
-  e[3] = fma(9.0, d2, fma(-4.0, d3, d4));
-  // smoothness of the three-point candidates: their second difference and
-  // their one-sided first difference at the centre
-  const double s0b = d1 + d2, s1b = fma(3.0, d2, -d3), s2b = fma(3.0, d1, -d0);
-  const double b0 = (13.0 / 48.0) * (D1 * D1) + (1.0 / 16.0) * (s0b * s0b);
-  const double b1 = (13.0 / 48.0) * (D2 * D2) + (1.0 / 16.0) * (s1b * s1b);
-  const double b2 = (13.0 / 48.0) * (D0 * D0) + (1.0 / 16.0) * (s2b * s2b);
-  // of the four-point candidate: its first, second and third derivative terms
-  const double s3a = fma(11.0, d2, fma(-7.0, d3, 2.0 * d4)), s3b = D2 - T2;
-  const double b3 = (1.0 / 144.0) * (s3a * s3a) + (13.0 / 48.0) * (s3b * s3b) + (781.0 / 2880.0) * (T2 * T2);
+// the constants, which are those of the formulas for f divided by powers of
+// two, so the same operations on h round exactly as they do on f (away from
+// underflow).  The smoothness indicators stay in the expanded form of the
+// definitions' sums, as the cut-offs of the reference solutions were taken
+// with it.  The candidate values in q[4] (those of f); returns the cut-off
+// pattern (bit k: candidate k kept).
+__device__ __forceinline__ unsigned teno6_decide(const double h[6], double CT, double q[4]) {
+  q[0] = (-h[1] + 5.0 * h[2] + 2.0 * h[3]) * (1.0 / 12.0);
+  q[1] = (2.0 * h[2] + 5.0 * h[3] - h[4]) * (1.0 / 12.0);
+  q[2] = (2.0 * h[0] - 7.0 * h[1] + 11.0 * h[2]) * (1.0 / 12.0);
+  q[3] = (3.0 * h[2] + 13.0 * h[3] - 5.0 * h[4] + h[5]) * (1.0 / 24.0);
+  const double s0a = h[1] - 2.0 * h[2] + h[3], s0b = h[1] - h[3];
+  const double s1a = h[2] - 2.0 * h[3] + h[4], s1b = 3.0 * h[2] - 4.0 * h[3] + h[4];
+  const double s2a = h[0] - 2.0 * h[1] + h[2], s2b = h[0] - 4.0 * h[1] + 3.0 * h[2];
+  const double s3a = -11.0 * h[2] + 18.0 * h[3] - 9.0 * h[4] + 2.0 * h[5];
+  const double s3b = 2.0 * h[2] - 5.0 * h[3] + 4.0 * h[4] - h[5];
+  const double s3c = -h[2] + 3.0 * h[3] - 3.0 * h[4] + h[5];
+  const double b0 = (13.0 / 48.0) * s0a * s0a + (1.0 / 16.0) * s0b * s0b;
+  const double b1 = (13.0 / 48.0) * s1a * s1a + (1.0 / 16.0) * s1b * s1b;
+  const double b2 = (13.0 / 48.0) * s2a * s2a + (1.0 / 16.0) * s2b * s2b;
+  const double b3 = (1.0 / 144.0) * s3a * s3a + (13.0 / 48.0) * s3b * s3b + (781.0 / 2880.0) * s3c * s3c;
   // six-point polynomial coefficients (origin at the centre of cell i)
-  const double a1 = (-341.0 / 11520.0) * d0 + (2444.0 / 11520.0) * d1 + (5034.0 / 11520.0) * d2 +
-                    (-1636.0 / 11520.0) * d3 + (259.0 / 11520.0) * d4;
-  const double a2 = fma(8.0, D1, -Q0) * (1.0 / 32.0);
-  const double a3 = (5.0 / 288.0) * T0 + (26.0 / 288.0) * T1 + (-7.0 / 288.0) * T2;
-  const double a4 = Q0 * (1.0 / 48.0);
-  const double a5 = P0 * (1.0 / 240.0);
+  const double a1 = (341.0 * h[0] - 2785.0 * h[1] - 2590.0 * h[2] + 6670.0 * h[3] - 1895.0 * h[4] + 259.0 * h[5]) *
+                    (1.0 / 11520.0);
+  const double a2 = -(h[0] - 12.0 * h[1] + 22.0 * h[2] - 12.0 * h[3] + h[4]) * (1.0 / 32.0);
+  const double a3 = -(5.0 * h[0] + 11.0 * h[1] - 70.0 * h[2] + 94.0 * h[3] - 47.0 * h[4] + 7.0 * h[5]) *
+                    (1.0 / 288.0);
+  const double a4 = (h[0] - 4.0 * h[1] + 6.0 * h[2] - 4.0 * h[3] + h[4]) * (1.0 / 48.0);
+  const double a5 = -(h[0] - 5.0 * h[1] + 10.0 * h[2] - 10.0 * h[3] + 5.0 * h[4] - h[5]) * (1.0 / 240.0);
   const double b6 = a1 * (a1 + 0.5 * a3 + 0.125 * a5) + a2 * ((13.0 / 3.0) * a2 + (21.0 / 5.0) * a4) +
                     a3 * ((3129.0 / 80.0) * a3 + (14127.0 / 224.0) * a5) + (87617.0 / 140.0) * a4 * a4 +
                     (252337135.0 / 16128.0) * a5 * a5;
@@ -118,19 +111,12 @@ __device__ __forceinline__ void teno6_weights(unsigned pat, double w[4]) {
   w[0] *= iw; w[1] *= iw; w[2] *= iw; w[3] *= iw;
 }
 
-// The weights of teno6_decide's increments e[k] in the face value:
-// sum_k w_k q_k = h_2/2 + sum_k W_k e_k (the normalised weights sum to one).
-__device__ __forceinline__ void teno6_wface(unsigned pat, double W[4]) {
-  teno6_weights(pat, W);
-  W[0] *= 1.0 / 12.0; W[1] *= 1.0 / 12.0; W[2] *= 1.0 / 12.0; W[3] *= 1.0 / 24.0;
-}
-
 // TENO6 reconstruction at x_{i+1/2} of one side of the split, from
 // h = 2 f_{i-2..i+3}.
 __device__ __forceinline__ double teno6_h(const double h[6], double CT) {
-  double e[4], W[4];
-  teno6_wface(teno6_decide(h, CT, e), W);
-  return 0.5 * h[2] + (W[0] * e[0] + W[1] * e[1] + W[2] * e[2] + W[3] * e[3]);
+  double q[4], w[4];
+  teno6_weights(teno6_decide(h, CT, q), w);
+  return w[0] * q[0] + w[1] * q[1] + w[2] * q[2] + w[3] * q[3];
 }
 
 // Third-order WENO-Z reconstruction at x_{i+1/2} (Don & Borges) from f_{i-1},

@@ -159,7 +159,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   __shared__ int s_tq[TAPE ? XFACE_MAX : 1];             // taped: the face's tape index (upper cell)
   __shared__ unsigned char s_td[TAPE ? XFACE_MAX : 1];   // taped: the face's axis
   __shared__ int s_nt;
-  __shared__ double s_w[16][4];        // TENO6 face weights of every cut-off pattern
+  __shared__ double s_w[16][4];        // TENO6 normalised weights of every cut-off pattern
   // before the variable loop the same memory holds the LF node speed, the
   // pressure and the sensor flags
   double* s_spd = s_U;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
   }
   if (t == 0) s_nt = 0;
   if constexpr (!LEAN) {
-    if (t < 16) teno6_wface(t, s_w[t]);
+    if (t < 16) teno6_weights(t, s_w[t]);
   }
   __syncthreads();
   // face f of the list: axis, stencil start slot (stencil positions j-3..j+2
@@ -435,12 +435,12 @@ __device__ __forceinline__ void conv_tile(int bl, const Member* __restrict__ mem
         sF[f] = weno3z_h(hp) + weno3z_h(hm);
         continue;
       }
-      double ep[4], em[4];
-      const unsigned pp = teno6_decide(hp, CT, ep), pm = teno6_decide(hm, CT, em);
+      double qp[4], qm[4];
+      const unsigned pp = teno6_decide(hp, CT, qp), pm = teno6_decide(hm, CT, qm);
       const double* wp = s_w[pp];
       const double* wm = s_w[pm];
-      sF[f] = 0.5 * (hp[2] + hm[2]) + ((wp[0] * ep[0] + wp[1] * ep[1] + wp[2] * ep[2] + wp[3] * ep[3]) +
-                                       (wm[0] * em[0] + wm[1] * em[1] + wm[2] * em[2] + wm[3] * em[3]));
+      sF[f] = (wp[0] * qp[0] + wp[1] * qp[1] + wp[2] * qp[2] + wp[3] * qp[3]) +
+              (wm[0] * qm[0] + wm[1] * qm[1] + wm[2] * qm[2] + wm[3] * qm[3]);
       if (TAPE) {
         // the cut-off pattern: bits 0-3 the + side's kept candidates, 4-7 the - side's
         const unsigned pat = pp | pm << 4;
