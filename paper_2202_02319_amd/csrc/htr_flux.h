@@ -67,9 +67,10 @@ __device__ __forceinline__ unsigned teno6_pattern(double b0, double b1, double b
 // the constants, which are those of the formulas for f divided by powers of
 // two, so the same operations on h round exactly as they do on f (away from
 // underflow).  The smoothness indicators stay in the expanded form of the
-// definitions' sums, as the cut-offs of the reference solutions were taken
-// with it.  The candidate values in q[4] (those of f); returns the cut-off
-// pattern (bit k: candidate k kept).
+// definitions' sums: an evaluation that rounds differently (from the
+// stencil's differences, say) takes another cut-off wherever rounding
+// decides one.  The candidate values in q[4] (those of f); returns the
+// cut-off pattern (bit k: candidate k kept).
 __device__ __forceinline__ unsigned teno6_decide(const double h[6], double CT, double q[4]) {
   q[0] = (-h[1] + 5.0 * h[2] + 2.0 * h[3]) * (1.0 / 12.0);
   q[1] = (2.0 * h[2] + 5.0 * h[3] - h[4]) * (1.0 / 12.0);
